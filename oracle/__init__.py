@@ -1,0 +1,448 @@
+"""Plain FP64 CPU oracle for MSPCG on the domain-wall / Moebius Dirac operator.
+
+TEST INFRASTRUCTURE ONLY.  The product (the HIP library and its binding) never
+imports, links or executes anything under oracle/.  Only tests/, the smoke
+check in __graft_entry__ and the cpu_baseline leg of bench.py use it.  It
+shares no code with the HIP path; the only common module is the seeded input
+generator (paper_1804_08593_amd.synth), which holds none of the arithmetic.
+
+Paper: Guo, Mawhinney, Tu, arXiv:1804.08593.
+  * Sec. 2.2, eq. (3): the DWF system is solved through its normal equations.
+  * Sec. 2.3, eqs. (4)-(5): with a zero initial guess, one multisplitting step
+    is a local solve A_s x_s = b_s per block; the preconditioner is the block
+    diagonal K = (+)_s A_s, applied approximately by a few local CG iterations
+    in lower precision ("local iterations").
+  * Sec. 3: the count of outer ("global") iterations is the quantity compared.
+The operator's formula is not in the paper; the standard Shamir / Moebius
+domain-wall definitions are used (see oracle.c).
+
+Every routine works on full-lattice complex128 numpy arrays
+  fermion [Ls][Lt][Lz][Ly][Lx][4][3],  gauge [4][Lt][Lz][Ly][Lx][3][3];
+"even fields" are full-lattice arrays whose odd sites are zero.
+
+Parity status: every function here is pinned by tests/test_oracle_*.py against
+closed forms, invariants, brute-force dense algebra or finite differences,
+except the outer-iteration count of MSPCG, which the paper gives only for an
+ensemble that is not available ("parity unpinned" for that count).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC_PATH = os.path.join(_HERE, "oracle.c")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc (-O2, OpenMP)."""
+    import subprocess
+
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall",
+                               "-o", tmp, _SRC_PATH, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or (
+                os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC_PATH)):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        I = ctypes.c_int
+        D = ctypes.c_double
+        L = ctypes.c_long
+        lib.orc_gamma.argtypes = [P]
+        lib.orc_set_threads.argtypes = [I]
+        lib.orc_get_threads.restype = I
+        lib.orc_hop.argtypes = [P, I, I, P, P, P, P, I]
+        lib.orc_hop_sites.argtypes = [P, I, I, P, P, P, P, I, P, L]
+        lib.orc_ktilde.argtypes = [P, I, D, P, P, I]
+        lib.orc_dwf.argtypes = [P, P, P, P, P, I]
+        lib.orc_m5.argtypes = [P, P, P, I]
+        lib.orc_parity_mask.argtypes = [P, I, P, I]
+        lib.orc_schur.argtypes = [P, P, P, P, P, I]
+        lib.orc_normal.argtypes = [P, P, P, P, P]
+        lib.orc_prepare.argtypes = [P, P, P, P, P]
+        lib.orc_reconstruct.argtypes = [P, P, P, P]
+        lib.orc_force.argtypes = [P, P, P, P, P]
+        _lib = lib
+    return _lib
+
+
+class _CAction(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int * 4), ("Ls", ctypes.c_int), ("antiperiodic_t", ctypes.c_int),
+                ("M5", ctypes.c_double), ("mf", ctypes.c_double),
+                ("b", ctypes.c_double), ("c", ctypes.c_double)]
+
+
+@dataclass
+class Action:
+    """Moebius domain-wall action: dims = (Lx, Ly, Lz, Lt); Shamir is b=1, c=0."""
+    dims: tuple
+    Ls: int
+    M5: float
+    mf: float
+    b: float = 1.0
+    c: float = 0.0
+    antiperiodic_t: bool = True
+    _c: _CAction = field(default=None, repr=False, compare=False)
+
+    def cstruct(self) -> _CAction:
+        s = _CAction()
+        for i in range(4):
+            s.L[i] = int(self.dims[i])
+        s.Ls = int(self.Ls)
+        s.antiperiodic_t = int(bool(self.antiperiodic_t))
+        s.M5, s.mf, s.b, s.c = float(self.M5), float(self.mf), float(self.b), float(self.c)
+        return s
+
+    @property
+    def V4(self) -> int:
+        return int(np.prod(self.dims))
+
+    @property
+    def fshape(self) -> tuple:
+        Lx, Ly, Lz, Lt = self.dims
+        return (self.Ls, Lt, Lz, Ly, Lx, 4, 3)
+
+    @property
+    def gshape(self) -> tuple:
+        Lx, Ly, Lz, Lt = self.dims
+        return (4, Lt, Lz, Ly, Lx, 3, 3)
+
+
+def set_threads(n: int) -> None:
+    _load().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_load().orc_get_threads())
+
+
+def gamma_matrices() -> np.ndarray:
+    """The four Euclidean gamma matrices of the chiral basis, [mu][4][4]."""
+    g = np.zeros((4, 4, 4), dtype=np.complex128)
+    _load().orc_gamma(g.ctypes.data)
+    return g
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data
+
+
+def _f(a: np.ndarray, shape) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    if a.shape != tuple(shape):
+        a = a.reshape(shape)
+    return a
+
+
+def _ivec(v):
+    return (ctypes.c_int * 4)(*[int(x) for x in v]) if v is not None else None
+
+
+def hop(act: Action, U, psi, dagger=False, block=None) -> np.ndarray:
+    """Wilson hopping term D_h (or D_h^+) applied to each s slice."""
+    U = _f(U, act.gshape)
+    psi = _f(psi, act.fshape)
+    out = np.empty_like(psi)
+    L = _ivec(act.dims)
+    _load().orc_hop(L, act.Ls, int(act.antiperiodic_t), _ivec(block), _p(U), _p(psi), _p(out),
+                    int(dagger))
+    return out
+
+
+def hop_sites(act: Action, U, psi, sites, dagger=False, block=None) -> np.ndarray:
+    """D_h psi at the given lexicographic output sites only: [Ls][nsites][4][3]."""
+    U = _f(U, act.gshape)
+    psi = _f(psi, act.fshape)
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    out = np.zeros(act.fshape, dtype=np.complex128)
+    _load().orc_hop_sites(_ivec(act.dims), act.Ls, int(act.antiperiodic_t), _ivec(block), _p(U),
+                          _p(psi), _p(out), int(dagger), _p(sites), len(sites))
+    return out.reshape(act.Ls, act.V4, 4, 3)[:, sites]
+
+
+def ktilde(act: Action, psi, dagger=False) -> np.ndarray:
+    psi = _f(psi, act.fshape)
+    out = np.empty_like(psi)
+    _load().orc_ktilde(_ivec(act.dims), act.Ls, float(act.mf), _p(psi), _p(out), int(dagger))
+    return out
+
+
+def dwf(act: Action, U, psi, dagger=False, block=None) -> np.ndarray:
+    """Full 5D operator D = D_W B + (1 - K) or its adjoint."""
+    U = _f(U, act.gshape)
+    psi = _f(psi, act.fshape)
+    out = np.empty_like(psi)
+    c = act.cstruct()
+    _load().orc_dwf(ctypes.byref(c), _ivec(block), _p(U), _p(psi), _p(out), int(dagger))
+    return out
+
+
+_M5_OPS = {"M5": 0, "M5dag": 1, "B": 2, "Bdag": 3, "M5inv": 4, "M5invdag": 5}
+
+
+def m5(act: Action, psi, which: str) -> np.ndarray:
+    """5D-local parts: M5 = alpha + beta K, B = b + c K, their adjoints and M5^-1."""
+    psi = _f(psi, act.fshape)
+    out = np.empty_like(psi)
+    c = act.cstruct()
+    _load().orc_m5(ctypes.byref(c), _p(psi), _p(out), _M5_OPS[which])
+    return out
+
+
+def parity_mask(act: Action, psi, parity: int) -> np.ndarray:
+    out = _f(psi, act.fshape).copy()
+    _load().orc_parity_mask(_ivec(act.dims), act.Ls, _p(out), int(parity))
+    return out
+
+
+def schur(act: Action, U, psi, dagger=False, block=None) -> np.ndarray:
+    """Even-odd Schur complement Mhat (or Mhat^+) on the even sites."""
+    U = _f(U, act.gshape)
+    psi = _f(psi, act.fshape)
+    out = np.empty_like(psi)
+    c = act.cstruct()
+    _load().orc_schur(ctypes.byref(c), _ivec(block), _p(U), _p(psi), _p(out), int(dagger))
+    return out
+
+
+def normal(act: Action, U, psi, block=None) -> np.ndarray:
+    """A = Mhat^+ Mhat (block-Dirichlet A_blk = (+)_s A_s when block is given)."""
+    U = _f(U, act.gshape)
+    psi = _f(psi, act.fshape)
+    out = np.empty_like(psi)
+    c = act.cstruct()
+    _load().orc_normal(ctypes.byref(c), _ivec(block), _p(U), _p(psi), _p(out))
+    return out
+
+
+def prepare(act: Action, U, b):
+    """(b'_e, bhat): b'_e = b_e - M_eo M5^-1 b_o and bhat = Mhat^+ b'_e."""
+    U = _f(U, act.gshape)
+    b = _f(b, act.fshape)
+    bp = np.empty_like(b)
+    bh = np.empty_like(b)
+    c = act.cstruct()
+    _load().orc_prepare(ctypes.byref(c), _p(U), _p(b), _p(bp), _p(bh))
+    return bp, bh
+
+
+def reconstruct(act: Action, U, b, x_even) -> np.ndarray:
+    """Full solution of D x = b from its even part: x_o = M5^-1 (b_o - M_oe x_e)."""
+    U = _f(U, act.gshape)
+    b = _f(b, act.fshape)
+    x = _f(x_even, act.fshape).copy()
+    c = act.cstruct()
+    _load().orc_reconstruct(ctypes.byref(c), _p(U), _p(b), _p(x))
+    return x
+
+
+def force(act: Action, U, X, Y) -> np.ndarray:
+    """Traceless Hermitian force F[mu][Lt][Lz][Ly][Lx][3][3] of S = phi^+ A^-1 phi.
+
+    X = A^-1 phi and Y = Mhat X (even fields); dS/deps = tr(T F_mu(x)) for the
+    variation U_mu(x) -> exp(i eps T) U_mu(x)."""
+    U = _f(U, act.gshape)
+    X = _f(X, act.fshape)
+    Y = _f(Y, act.fshape)
+    F = np.empty(act.gshape, dtype=np.complex128)
+    c = act.cstruct()
+    _load().orc_force(ctypes.byref(c), _p(U), _p(X), _p(Y), _p(F))
+    return F
+
+
+# ---------------------------------------------------------------------------
+# Solvers (numpy loops over the operators above)
+# ---------------------------------------------------------------------------
+
+def dot(u, v) -> complex:
+    """<u, v> = sum conj(u) v (numpy pairwise summation; no BLAS, whose spinning
+    threads would contend with the OpenMP ones of the C operators)."""
+    return complex(np.sum(np.conj(u) * v))
+
+
+def norm2(u) -> float:
+    return float(np.sum(u.real ** 2 + u.imag ** 2))
+
+
+@dataclass
+class SolveInfo:
+    iters: int = 0
+    true_rel_resid: float = float("nan")
+    history: list = field(default_factory=list)
+    converged: bool = False
+
+
+def cg(act: Action, U, bhat, tol=1e-10, maxiter=10000, x0=None, block=None):
+    """Plain CG on A x = bhat (normal equations of the Schur operator).
+
+    The stop test is the true relative residual ||bhat - A x|| / ||bhat|| <= tol,
+    recomputed whenever the iterated residual says converged; if it fails, the
+    iterated residual is replaced by the true one and CG continues."""
+    A = lambda v: normal(act, U, v, block)
+    bnorm = np.sqrt(norm2(bhat))
+    info = SolveInfo()
+    x = np.zeros_like(bhat) if x0 is None else x0.copy()
+    r = bhat - A(x) if x0 is not None else bhat.copy()
+    if bnorm == 0:
+        info.converged, info.true_rel_resid = True, 0.0
+        return x, info
+    p = r.copy()
+    rr = norm2(r)
+    for k in range(1, maxiter + 1):
+        q = A(p)
+        alpha = rr / dot(p, q).real
+        x += alpha * p
+        r -= alpha * q
+        rr_new = norm2(r)
+        info.iters = k
+        info.history.append(np.sqrt(rr_new) / bnorm)
+        if np.sqrt(rr_new) / bnorm <= tol:
+            rt = bhat - A(x)
+            tr = np.sqrt(norm2(rt)) / bnorm
+            if tr <= tol:
+                info.converged, info.true_rel_resid = True, tr
+                return x, info
+            r = rt
+            rr_new = norm2(r)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    info.true_rel_resid = np.sqrt(norm2(bhat - A(x))) / bnorm
+    return x, info
+
+
+def block_ids(act: Action, block) -> np.ndarray:
+    """Block index of every lexicographic site, [Lt][Lz][Ly][Lx]."""
+    Lx, Ly, Lz, Lt = act.dims
+    bx, by, bz, bt = block
+    t, z, y, x = np.meshgrid(np.arange(Lt), np.arange(Lz), np.arange(Ly), np.arange(Lx),
+                             indexing="ij")
+    nbx, nby, nbz = Lx // bx, Ly // by, Lz // bz
+    return (((t // bt) * nbz + z // bz) * nby + y // by) * nbx + x // bx
+
+
+def _block_dot(u, v, ids, nblk) -> np.ndarray:
+    """Per-block <u, v>: sum over s, spin, colour and the sites of each block."""
+    site = np.sum(np.conj(u) * v, axis=(0, 5, 6))  # [Lt][Lz][Ly][Lx]
+    return (np.bincount(ids.ravel(), weights=site.real.ravel(), minlength=nblk)
+            + 1j * np.bincount(ids.ravel(), weights=site.imag.ravel(), minlength=nblk))
+
+
+def block_precond_op(act: Action, U, p, block, mode: str = "literal") -> np.ndarray:
+    """The preconditioner K = (+)_s A_s applied to p (Sec. 2.3 eq. (5), Fig. 3).
+
+    mode "literal": A_s = P_s A P_s, the diagonal block of A = Mhat^+ Mhat with
+      every off-block entry set to zero, exactly as the paper defines it; it
+      keeps the paths that leave block s and come back.  Computed from the
+      definition: one application of A per block, masked before and after.
+    mode "dirichlet": A_s = Mhat_s^+ Mhat_s with every hop between different
+      blocks dropped (a cheaper operator that is not the paper's block)."""
+    if mode == "dirichlet":
+        return normal(act, U, p, block)
+    if mode != "literal":
+        raise ValueError(mode)
+    ids = block_ids(act, block)
+    out = np.zeros_like(p)
+    for k in range(int(ids.max()) + 1):
+        m = (ids == k)[None, ..., None, None]
+        out += m * normal(act, U, m * p)
+    return out
+
+
+def inner_block_cg(act: Action, U, r, block, l: int, mode: str = "literal") -> np.ndarray:
+    """Sloppy preconditioner z = K_l^-1 r (Sec. 2.3 eqs. (4)-(5), "local iterations").
+
+    For every block independently: l CG iterations on A_s z_s = r_s from z_s = 0
+    (the zero initial guess that turns the multisplitting step, eq. (2), into
+    the local solve of eq. (4)).  A block whose <rho,rho> or <p, A_s p> is zero
+    keeps its current z."""
+    ids = block_ids(act, block)
+    nblk = int(ids.max()) + 1
+    bcast = lambda c: c[ids][None, ..., None, None]
+    z = np.zeros_like(r)
+    rho = r.copy()
+    p = rho.copy()
+    gam = _block_dot(rho, rho, ids, nblk).real
+    active = gam > 0
+    for _ in range(l):
+        w = block_precond_op(act, U, p, block, mode)
+        pw = _block_dot(p, w, ids, nblk).real
+        active &= pw > 0
+        a = np.where(active, gam / np.where(active, pw, 1.0), 0.0)
+        z += bcast(a) * p
+        rho -= bcast(a) * w
+        gam_new = _block_dot(rho, rho, ids, nblk).real
+        beta = np.where(active, gam_new / np.where(gam > 0, gam, 1.0), 0.0)
+        active &= gam_new > 0
+        p = rho + bcast(beta) * p
+        gam = gam_new
+    return z
+
+
+def mspcg(act: Action, U, bhat, block, l: int, tol=1e-10, maxiter=10000, x0=None,
+          mode: str = "literal"):
+    """Flexible preconditioned CG with K_l^-1 = inner_block_cg (Sec. 2.3).
+
+    The preconditioner is inexact, so beta takes the flexible (Polak-Ribiere)
+    form  beta = Re<z_new, r_new - r> / Re<z, r>.  Stop test as in cg()."""
+    A = lambda v: normal(act, U, v)
+    K = lambda v: inner_block_cg(act, U, v, block, l, mode)
+    bnorm = np.sqrt(norm2(bhat))
+    info = SolveInfo()
+    x = np.zeros_like(bhat) if x0 is None else x0.copy()
+    r = bhat - A(x) if x0 is not None else bhat.copy()
+    if bnorm == 0:
+        info.converged, info.true_rel_resid = True, 0.0
+        return x, info
+    z = K(r)
+    p = z.copy()
+    zr = dot(z, r).real
+    for k in range(1, maxiter + 1):
+        q = A(p)
+        alpha = zr / dot(p, q).real
+        x += alpha * p
+        r_new = r - alpha * q
+        info.iters = k
+        rel = np.sqrt(norm2(r_new)) / bnorm
+        info.history.append(rel)
+        if rel <= tol:
+            rt = bhat - A(x)
+            tr = np.sqrt(norm2(rt)) / bnorm
+            if tr <= tol:
+                info.converged, info.true_rel_resid = True, tr
+                return x, info
+            r_new = rt
+        z_new = K(r_new)
+        beta = dot(z_new, r_new - r).real / zr
+        zr = dot(z_new, r_new).real
+        p = z_new + beta * p
+        r = r_new
+        z = z_new
+    info.true_rel_resid = np.sqrt(norm2(bhat - A(x))) / bnorm
+    return x, info
+
+
+def solve(act: Action, U, b, tol=1e-10, maxiter=10000, precond=None):
+    """Full solution of D x = b through the even-odd normal equations.
+
+    precond = None: plain CG; precond = (block, l) or (block, l, mode): MSPCG."""
+    _, bhat = prepare(act, U, b)
+    if precond is None:
+        xe, info = cg(act, U, bhat, tol, maxiter)
+    else:
+        mode = precond[2] if len(precond) > 2 else "literal"
+        xe, info = mspcg(act, U, bhat, precond[0], precond[1], tol, maxiter, mode=mode)
+    return reconstruct(act, U, b, xe), info
