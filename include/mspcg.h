@@ -1,0 +1,209 @@
+/*
+ * mspcg.h -- C ABI of the MI355X (gfx950) library for the multisplitting-
+ * preconditioned conjugate gradient (MSPCG) solve of the domain-wall /
+ * Moebius Dirac equation.
+ *
+ * Paper: D. Guo, R. Mawhinney, J. Tu, "Solving DWF Dirac Equation Using
+ * Multisplitting Preconditioned Conjugate Gradient", arXiv:1804.08593.
+ *   Sec. 2.2, eq. (3): the non-Hermitian DWF system D x = b is solved through
+ *     its normal equations; here the even-odd Schur complement Mhat of D is
+ *     used and CG runs on A = Mhat^+ Mhat.
+ *   Sec. 2.3, eqs. (4)-(5), Fig. 3: the preconditioner K = (+)_s A_s keeps the
+ *     diagonal blocks of A (one block per node, all other entries zero); it is
+ *     applied approximately by l local CG iterations from a zero guess, in
+ *     lower precision, with no communication between blocks.
+ *   Sec. 3: the figure of merit is the number of global (outer) iterations.
+ *
+ * Operator conventions (standard Shamir / Moebius domain-wall fermions; the
+ * paper only says the operator is a Wilson operator with a large mass times a
+ * fictitious fifth dimension, Sec. 2.2):
+ *   D   = D_W (b + c K) + (1 - K),   D_W = (4 - M5) - D_h / 2,
+ *   D_h psi(x) = sum_mu eta (1 - g_mu) U_mu(x) psi(x+mu) + eta (1 + g_mu) U_mu(x-mu)^+ psi(x-mu),
+ *   (K psi)_s = P- psi_{s+1} + P+ psi_{s-1},  psi_{Ls} = -mf psi_0,  psi_{-1} = -mf psi_{Ls-1},
+ *   chiral basis g_k = [[0, -i s_k], [i s_k, 0]], g_t = [[0, 1], [1, 0]],
+ *   g5 = diag(1, 1, -1, -1), P+- = (1 +- g5)/2, eta = -1 on hops that cross
+ *   the time boundary when antiperiodic_t is set.
+ *   Even-odd: Mhat = M5op - D_h^eo (b + c K) M5op^-1 D_h^oe (b + c K) / 4 on the
+ *   even sites (parity of x+y+z+t), M5op = ((4-M5) b + 1) + ((4-M5) c - 1) K.
+ *
+ * Boundary layouts (device memory, caller-owned, complex double interleaved):
+ *   fermion  [Ls][Lt][Lz][Ly][Lx][4 spin][3 colour]
+ *   gauge    [4 mu][Lt][Lz][Ly][Lx][3 row][3 col]   (mu = 0:x 1:y 2:z 3:t)
+ *   force    same layout as gauge
+ * "Even fields" use the fermion layout; only their even sites are read, and
+ * the odd sites of an even-field output are set to zero.
+ *
+ * Ownership and synchronisation: the library never frees or retains a caller
+ * pointer after a call returns.  The context owns its internal gauge copies,
+ * work vectors and timing events; mspcg_destroy releases them.  All work is
+ * enqueued on the given stream (0 = the null stream).  mspcg_apply and
+ * mspcg_precond are asynchronous; mspcg_solve, mspcg_solve_batch and
+ * mspcg_force return after the stream has completed because their statistics
+ * are host-visible.  A context is not thread-safe: use one per (device,
+ * stream).  Every call returns 0 on success or a negative MSPCG_E* code; no
+ * exception crosses the ABI.  mspcg_strerror gives the text.
+ */
+#ifndef MSPCG_H
+#define MSPCG_H
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MSPCG_VERSION 1
+
+enum {
+    MSPCG_OK = 0,
+    MSPCG_EINVAL = -1,    /* invalid argument (dims, Ls, parameters, null pointer) */
+    MSPCG_ENOMEM = -2,    /* device allocation failed */
+    MSPCG_EHIP = -3,      /* a HIP runtime call or kernel launch failed */
+    MSPCG_ENOGAUGE = -4,  /* operator used before mspcg_load_gauge */
+    MSPCG_ENOCONV = -5,   /* solve stopped at maxiter; x holds the last iterate */
+    MSPCG_EBREAKDOWN = -6,/* non-positive curvature or non-finite value in a solve */
+    MSPCG_EUNSUPPORTED = -7 /* Ls not compiled in, or an unsupported combination */
+};
+
+typedef struct mspcg_ctx mspcg_ctx;
+
+/* Action parameters.  dims = (Lx, Ly, Lz, Lt), every extent even; Ls >= 2 and
+ * one of the compiled extents (2 4 6 8 10 12 16 20 24 32); Shamir is b=1, c=0. */
+typedef struct {
+    int dims[4];
+    int Ls;
+    double M5;
+    double mf;
+    double b;
+    double c;
+    int antiperiodic_t;
+} mspcg_action;
+
+/* Operators for mspcg_apply. */
+enum {
+    MSPCG_OP_D = 0,        /* full 5D operator D on a full field */
+    MSPCG_OP_DDAG = 1,     /* D^+ */
+    MSPCG_OP_HOP = 2,      /* Wilson hop D_h (both parities, every s slice) */
+    MSPCG_OP_HOPDAG = 3,   /* D_h^+ */
+    MSPCG_OP_MHAT = 4,     /* even-odd Schur complement Mhat on an even field */
+    MSPCG_OP_MHATDAG = 5,  /* Mhat^+ */
+    MSPCG_OP_A = 6,        /* A = Mhat^+ Mhat on an even field */
+    MSPCG_OP_M5INV = 7,    /* M5op^-1 on a full field (5D-local) */
+    MSPCG_OP_PREPARE = 8,  /* even field bhat = Mhat^+ (b_e - M_eo M5op^-1 b_o) from full b */
+    MSPCG_OP_KBLOCK = 9    /* preconditioner K = (+)_s A_s on an even field (needs blocks) */
+};
+
+/* Arithmetic / storage precision of an operator application. */
+enum {
+    MSPCG_FP64 = 0,
+    MSPCG_FP32 = 1,
+    MSPCG_FP16 = 2  /* FP16 storage of spinors (per-(x,s) FP32 scale) and links, FP32 math */
+};
+
+/* Solvers. */
+enum {
+    MSPCG_SOLVER_CG = 0,       /* plain FP64 CG on A */
+    MSPCG_SOLVER_MIXED_CG = 1, /* FP32 CG iterations, FP64 solution and reliable updates */
+    MSPCG_SOLVER_MSPCG = 2     /* FP64 flexible outer PCG, sloppy block preconditioner */
+};
+
+/* Block decomposition of the preconditioner.  block[mu] divides dims[mu] and
+ * is even.  pad = depth of the padded domain on which each block's operator
+ * is evaluated: pad >= 2 gives exactly the paper's A_s = P_s A P_s (Fig. 3:
+ * the diagonal block of A, including the paths that leave the block and come
+ * back); pad = 0 drops every hop between blocks (A_s = Mhat_s^+ Mhat_s with
+ * a Dirichlet-cut Mhat_s); pad = 1 lies in between. */
+typedef struct {
+    int block[4];
+    int pad;
+} mspcg_blocking;
+
+typedef struct {
+    double tol;           /* stop when |bhat - A x| / |bhat| <= tol (true residual, FP64) */
+    int maxiter;          /* outer iterations */
+    int solver;           /* MSPCG_SOLVER_* */
+    int use_x0;           /* 1: x holds the initial guess on entry (even part used) */
+    mspcg_blocking blocking; /* MSPCG only */
+    int inner_iters;      /* l: local CG iterations per outer iteration (MSPCG) */
+    int inner_prec;       /* MSPCG_FP16 / FP32 / FP64 for the local solves (MSPCG) */
+    int check_every;      /* host convergence poll interval in iterations (0: auto) */
+    double delta;         /* reliable-update threshold of the mixed CG (0: 0.1) */
+    int timing;           /* 1: record per-kernel-class times with HIP events */
+} mspcg_solve_params;
+
+/* Kernel classes reported by the timing facility. */
+enum {
+    MSPCG_KC_HOP64 = 0,  /* FP64 whole-lattice hop (with fused 5D epilogues) */
+    MSPCG_KC_HOP32 = 1,  /* FP32 whole-lattice hop */
+    MSPCG_KC_HOPDOM = 2, /* block-domain hop of the local solves (inner precision) */
+    MSPCG_KC_FIVED = 3,  /* 5D-only kernels */
+    MSPCG_KC_BLAS = 4,   /* vector updates, reductions, conversions */
+    MSPCG_KC_COUNT = 5
+};
+
+typedef struct {
+    int outer_iters;       /* global iterations */
+    int inner_iters_total; /* local iterations summed over outer iterations */
+    int restarts;          /* true-residual replacements */
+    int converged;
+    double true_rel_resid; /* |bhat - A x| / |bhat| in FP64 at exit */
+    double seconds;        /* wall time of the solve on the stream */
+    double* resid_history; /* caller buffer (may be NULL): |r_k| / |bhat| per outer iteration */
+    int resid_history_cap;
+    int resid_history_len;
+    double kernel_ms[MSPCG_KC_COUNT];     /* timing = 1: summed kernel time per class */
+    long kernel_launches[MSPCG_KC_COUNT];
+    double kernel_bytes[MSPCG_KC_COUNT];  /* algorithmic bytes of those launches */
+} mspcg_solve_stats;
+
+/* Create a context on HIP device `device`.  Validates the action: every
+ * extent even and >= 2, Ls compiled in, b != 0, finite parameters, and the
+ * invertibility of M5op (1 + mf q^Ls != 0, q = -beta/alpha).  MSPCG_EINVAL
+ * otherwise. */
+int mspcg_create(const mspcg_action* action, int device, mspcg_ctx** ctx);
+void mspcg_destroy(mspcg_ctx* ctx);
+const char* mspcg_strerror(int code);
+int mspcg_version(void);
+
+/* Copy the gauge field (boundary layout, complex128 device pointer) into the
+ * context's internal FP64/FP32/FP16 layouts, folding in the boundary sign. */
+int mspcg_load_gauge(mspcg_ctx* ctx, const void* U_dev, hipStream_t stream);
+
+/* out = op(in) in precision prec (FP64 or FP32; FP16 for MSPCG_OP_KBLOCK).
+ * in/out: complex128 device pointers in the fermion layout, in != out.
+ * MSPCG_OP_KBLOCK uses the blocking set by mspcg_set_blocking. */
+int mspcg_apply(mspcg_ctx* ctx, int op, int prec, const void* in_dev, void* out_dev,
+                hipStream_t stream);
+
+/* Blocking used by MSPCG_OP_KBLOCK and mspcg_precond. */
+int mspcg_set_blocking(mspcg_ctx* ctx, const mspcg_blocking* blocking);
+
+/* z = K_l^-1 r: l local CG iterations per block from a zero guess, in
+ * precision prec (Sec. 2.3).  r, z: even fields (complex128). */
+int mspcg_precond(mspcg_ctx* ctx, int inner_iters, int prec, const void* r_dev, void* z_dev,
+                  hipStream_t stream);
+
+/* Solve D x = b (b, x: full fields, complex128).  The even part is solved on
+ * A = Mhat^+ Mhat and the odd part reconstructed.  On MSPCG_ENOCONV x holds
+ * the last iterate and stats are filled.  stats may be NULL. */
+int mspcg_solve(mspcg_ctx* ctx, const void* b_dev, void* x_dev, const mspcg_solve_params* params,
+                mspcg_solve_stats* stats, hipStream_t stream);
+
+/* Solve n independent systems (one context each, possibly of different sizes)
+ * with the same parameters; the outer iterations of all still-active systems
+ * are interleaved on one stream.  stats: array of n (may be NULL). */
+int mspcg_solve_batch(mspcg_ctx* const* ctxs, int n, const void* const* b_dev, void* const* x_dev,
+                      const mspcg_solve_params* params, mspcg_solve_stats* stats,
+                      hipStream_t stream);
+
+/* HMC fermion force of S = phi^+ A^-1 phi.  X = A^-1 phi and Y = Mhat X are
+ * even fields; F (gauge layout) receives, per link, the traceless Hermitian
+ * matrix with dS/deps = tr(T F_mu(x)) for U_mu(x) -> exp(i eps T) U_mu(x). */
+int mspcg_force(mspcg_ctx* ctx, const void* X_dev, const void* Y_dev, void* F_dev,
+                hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSPCG_H */

@@ -1,0 +1,316 @@
+// Fifth-dimension-only kernel, FP64 BLAS-1 with fused reductions, per-domain
+// (block) CG vector updates for the sloppy inner solve, and the fixed-order
+// reductions that make every result bitwise reproducible (no float atomics).
+#include "common.h"
+#include "fived.h"
+#include "kernels.h"
+
+namespace mspcg {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ void block_reduce_store(double v, double* dst) {
+    __shared__ double red[kThreads / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) t += red[i];
+        *dst = t;
+    }
+}
+
+template <class S, int LS>
+__global__ __launch_bounds__(256) void fived_kernel(FiveDArgs<S> a) {
+    using T = typename S::real;
+    constexpr int SPB = 256 / LS;
+    constexpr int SITE_STRIDE = LS * 12 + 1;
+    __shared__ cx<T> lds[SPB * SITE_STRIDE];
+    if (a.done && *a.done) return;
+    const int d = blockIdx.y;
+    const int sl = threadIdx.x / LS;
+    const int s = threadIdx.x - sl * LS;
+    const long cb = (long)blockIdx.x * SPB + sl;
+    const bool active = sl < SPB && cb < a.Vh;
+    const long idx = ((long)d * a.Vh + cb) * LS + s;
+    cx<T> v[12];
+    if (active) {
+        load_spinor<S>(a.in, idx, v);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) lds[sl * SITE_STRIDE + s * 12 + c] = v[c];
+    }
+    __syncthreads();
+    for (int ch = threadIdx.x; ch < SPB * 12; ch += blockDim.x) {
+        const int csl = ch / 12, comp = ch - csl * 12;
+        cx<T> w[LS];
+#pragma unroll
+        for (int t = 0; t < LS; ++t) w[t] = lds[csl * SITE_STRIDE + t * 12 + comp];
+        apply_prog<LS, T>(a.p, comp < 6, (T)a.mf, w);
+#pragma unroll
+        for (int t = 0; t < LS; ++t) lds[csl * SITE_STRIDE + t * 12 + comp] = w[t];
+    }
+    __syncthreads();
+    double n2 = 0;
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            v[c] = lds[sl * SITE_STRIDE + s * 12 + c];
+            n2 += (double)v[c].re * v[c].re + (double)v[c].im * v[c].im;
+        }
+        store_spinor<S>(a.out, idx, v);
+    }
+    if (a.partials) block_reduce_store(n2, a.partials + (long)d * gridDim.x + blockIdx.x);
+}
+
+template <class S, int LS>
+void fived_launch_ls(const FiveDArgs<S>& a, int ndom, hipStream_t st) {
+    constexpr int SPB = 256 / LS;
+    hipLaunchKernelGGL((fived_kernel<S, LS>), dim3((unsigned)((a.Vh + SPB - 1) / SPB), ndom),
+                       dim3(SPB * LS), 0, st, a);
+}
+
+// ---- reductions ----------------------------------------------------------
+
+// One workgroup per output: fixed-order strided sums, then a fixed tree.
+__global__ void reduce_rows_kernel(const double* partials, int nparts, double* out) {
+    const double* p = partials + (long)blockIdx.x * nparts;
+    double v = 0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) v += p[i];
+    block_reduce_store(v, out + blockIdx.x);
+}
+
+__device__ double block_sum_all(const double* p, int n) {
+    __shared__ double red2[kThreads];
+    double v = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
+    red2[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red2[threadIdx.x] += red2[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double r = red2[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ void cg_alpha_kernel(DevScalars* sc, const double* partials, int nparts) {
+    if (sc->done) return;
+    const double pq = block_sum_all(partials, nparts);
+    if (threadIdx.x == 0) {
+        sc->pq = pq;
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            sc->breakdown = 1;
+            sc->done = 1;
+            sc->alpha = 0.0;
+        } else {
+            sc->alpha = sc->rr / pq;
+        }
+    }
+}
+
+__global__ void cg_beta_kernel(DevScalars* sc, const double* partials, int nparts, double* hist,
+                               int hist_cap) {
+    if (sc->done) return;
+    const double rr = block_sum_all(partials, nparts);
+    if (threadIdx.x == 0) {
+        sc->beta = rr / sc->rr;
+        sc->rr = rr;
+        const int k = sc->iter;
+        if (hist && k < hist_cap) hist[k] = rr;
+        sc->iter = k + 1;
+        if (!isfinite(rr)) {
+            sc->breakdown = 1;
+            sc->done = 1;
+        } else if (rr <= sc->tol2) {
+            sc->done = 1;
+        }
+    }
+}
+
+// x += alpha p ; r -= alpha q ; partial |r|^2.  Flat over 12*N complex.
+__global__ void cg_update_xr_kernel(double2* x, double2* r, const double2* p, const double2* q,
+                                    long n, const DevScalars* sc, double* partials) {
+    if (sc->done) return;
+    const double al = sc->alpha;
+    double acc = 0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        const double2 pv = p[i], qv = q[i];
+        double2 xv = x[i], rv = r[i];
+        xv.x += al * pv.x;
+        xv.y += al * pv.y;
+        rv.x -= al * qv.x;
+        rv.y -= al * qv.y;
+        x[i] = xv;
+        r[i] = rv;
+        acc += rv.x * rv.x + rv.y * rv.y;
+    }
+    block_reduce_store(acc, partials + blockIdx.x);
+}
+
+// which = 0: p = r + beta p ; which = 1: p = r + (zr/zr_old) p handled by caller via beta
+__global__ void xpay_kernel(double2* p, const double2* r, long n, const DevScalars* sc) {
+    if (sc->done) return;
+    const double b = sc->beta;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        const double2 rv = r[i];
+        double2 pv = p[i];
+        pv.x = rv.x + b * pv.x;
+        pv.y = rv.y + b * pv.y;
+        p[i] = pv;
+    }
+}
+
+__global__ void sub_norm_kernel(double2* r, const double2* b, const double2* ax, long n,
+                                double* partials) {
+    double acc = 0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        const double2 bv = b[i], av = ax[i];
+        const double2 rv = make_double2(bv.x - av.x, bv.y - av.y);
+        r[i] = rv;
+        acc += rv.x * rv.x + rv.y * rv.y;
+    }
+    block_reduce_store(acc, partials + blockIdx.x);
+}
+
+__global__ void copy_norm_kernel(double2* dst, const double2* src, long n, double* partials) {
+    double acc = 0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        const double2 v = src[i];
+        if (dst) dst[i] = v;
+        acc += v.x * v.x + v.y * v.y;
+    }
+    block_reduce_store(acc, partials + blockIdx.x);
+}
+
+// Re<z, r> and Re<z, q> partials: [0..nparts) and [nparts..2 nparts)
+__global__ void dot2_kernel(const double2* z, const double2* r, const double2* q, long n,
+                            double* partials, long nparts) {
+    double a = 0, b = 0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        const double2 zv = z[i], rv = r[i], qv = q[i];
+        a += zv.x * rv.x + zv.y * rv.y;
+        b += zv.x * qv.x + zv.y * qv.y;
+    }
+    block_reduce_store(a, partials + blockIdx.x);
+    __syncthreads();
+    block_reduce_store(b, partials + nparts + blockIdx.x);
+}
+
+__global__ void axpy_kernel(double2* y, const double2* x, double a, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        const double2 xv = x[i];
+        double2 yv = y[i];
+        yv.x += a * xv.x;
+        yv.y += a * xv.y;
+        y[i] = yv;
+    }
+}
+
+int last_error() { return hipGetLastError() == hipSuccess ? 0 : -2; }
+
+}  // namespace
+
+template <class S>
+int launch_fived(const FiveDArgs<S>& a, int Ls, int ndom, hipStream_t st) {
+    switch (Ls) {
+#define MSPCG_CASE(L) \
+    case L: fived_launch_ls<S, L>(a, ndom, st); break;
+        MSPCG_LS_LIST(MSPCG_CASE)
+#undef MSPCG_CASE
+        default: return -1;
+    }
+    return last_error();
+}
+template int launch_fived<F64>(const FiveDArgs<F64>&, int, int, hipStream_t);
+template int launch_fived<F32>(const FiveDArgs<F32>&, int, int, hipStream_t);
+template int launch_fived<F16>(const FiveDArgs<F16>&, int, int, hipStream_t);
+
+long fived_grid_x(long Vh, int Ls) {
+    const int spb = 256 / Ls;
+    return (Vh + spb - 1) / spb;
+}
+
+// Vector kernels use a fixed grid so partial counts are known in advance.
+long blas_grid_x(long n) {
+    long g = (n + kThreads - 1) / kThreads;
+    return g < 2048 ? (g < 1 ? 1 : g) : 2048;
+}
+
+int launch_reduce_sum(const double* partials, int nparts, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(kThreads), 0, st, partials, nparts, out);
+    return last_error();
+}
+
+int launch_reduce_domains(const double* partials, int ndom, int nparts, double* out,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(ndom), dim3(kThreads), 0, st, partials, nparts,
+                       out);
+    return last_error();
+}
+
+int launch_cg_alpha(DevScalars* sc, const double* partials, int nparts, hipStream_t st) {
+    hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(kThreads), 0, st, sc, partials, nparts);
+    return last_error();
+}
+
+int launch_cg_beta(DevScalars* sc, const double* partials, int nparts, double* hist,
+                   int hist_cap, hipStream_t st) {
+    hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(kThreads), 0, st, sc, partials, nparts, hist,
+                       hist_cap);
+    return last_error();
+}
+
+int launch_cg_update_xr(double2* x, double2* r, const double2* p, const double2* q, long N,
+                        const DevScalars* sc, double* partials, long nparts, hipStream_t st) {
+    hipLaunchKernelGGL(cg_update_xr_kernel, dim3((unsigned)nparts), dim3(kThreads), 0, st, x, r, p,
+                       q, 12 * N, sc, partials);
+    return last_error();
+}
+
+int launch_xpay(double2* p, const double2* r, long N, const DevScalars* sc, int,
+                hipStream_t st) {
+    hipLaunchKernelGGL(xpay_kernel, dim3((unsigned)blas_grid_x(12 * N)), dim3(kThreads), 0, st, p,
+                       r, 12 * N, sc);
+    return last_error();
+}
+
+int launch_sub_norm(double2* r, const double2* b, const double2* ax, long N, double* partials,
+                    long nparts, hipStream_t st) {
+    hipLaunchKernelGGL(sub_norm_kernel, dim3((unsigned)nparts), dim3(kThreads), 0, st, r, b, ax,
+                       12 * N, partials);
+    return last_error();
+}
+
+int launch_copy_norm(double2* dst, const double2* src, long N, double* partials, long nparts,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(copy_norm_kernel, dim3((unsigned)nparts), dim3(kThreads), 0, st, dst, src,
+                       12 * N, partials);
+    return last_error();
+}
+
+int launch_dot2(const double2* z, const double2* r, const double2* q, long N, double* partials,
+                long nparts, hipStream_t st) {
+    hipLaunchKernelGGL(dot2_kernel, dim3((unsigned)nparts), dim3(kThreads), 0, st, z, r, q, 12 * N,
+                       partials, nparts);
+    return last_error();
+}
+
+int launch_axpy(double2* y, const double2* x, double a, long N, hipStream_t st) {
+    hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)blas_grid_x(12 * N)), dim3(kThreads), 0, st, y,
+                       x, a, 12 * N);
+    return last_error();
+}
+
+}  // namespace mspcg

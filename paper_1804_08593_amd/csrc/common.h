@@ -1,0 +1,178 @@
+// Shared device-side definitions of the MSPCG HIP library (gfx950).
+//
+// Internal data layout (all on device, chosen for coalesced wave64 access):
+//   * A "box" is a 4D sub-lattice [0,E0)x[0,E1)x[0,E2)x[0,E3) placed at offset
+//     `off` from the origin of its domain; the whole periodic lattice is the
+//     special case of one domain whose boxes are the lattice itself.
+//   * Sites of one parity in a box are numbered by cb = lex/2 with
+//     lex = ((t*E2 + z)*E1 + y)*E0 + x (E0 even).
+//   * Spinor fields are structure-of-arrays over 12 complex components:
+//     element (comp, domain d, cb, s) lives at comp*N + (d*Vh + cb)*Ls + s,
+//     N = ndomains*Vh*Ls.  A thread owns one (site, s) and consecutive lanes
+//     hold consecutive s, so every component access of a wave is contiguous.
+//   * FP16 fields store value/scale as __half2 per complex component plus one
+//     FP32 scale per (site, s) (the max |real| over its 24 reals).
+//   * Links are stored per output parity and per direction as
+//     [parity][8][9][Vh_linkbox]: dirs 0..3 hold U_mu(x), dirs 4..7 hold
+//     U_mu(x-mu)^+ (already daggered), with the antiperiodic-time sign folded
+//     in.  Each link is read once per site and reused by all Ls lanes.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace mspcg {
+
+constexpr int kMaxLs = 32;
+constexpr int kMaxDomains = 4096;
+
+template <typename T>
+struct cx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// a += b * c
+template <typename T>
+__device__ __forceinline__ void cfma(cx<T>& a, cx<T> b, cx<T> c) {
+    a.re += b.re * c.re - b.im * c.im;
+    a.im += b.re * c.im + b.im * c.re;
+}
+
+// Storage policies.  `real` is the arithmetic type; `elem` the stored complex.
+struct F64 {
+    using real = double;
+    using elem = double2;
+    static constexpr bool has_scale = false;
+    static constexpr int bytes_spinor = 192;  // 12 complex x 16 B
+    static constexpr int bytes_link = 144;
+};
+struct F32 {
+    using real = float;
+    using elem = float2;
+    static constexpr bool has_scale = false;
+    static constexpr int bytes_spinor = 96;
+    static constexpr int bytes_link = 72;
+};
+struct F16 {
+    using real = float;
+    using elem = __half2;
+    static constexpr bool has_scale = true;
+    static constexpr int bytes_spinor = 52;  // 12 x 4 B + 4 B scale
+    static constexpr int bytes_link = 36;
+};
+
+// A field: 12 component arrays of N elements (+ scales for FP16).
+template <class S>
+struct Field {
+    typename S::elem* data;
+    float* scale;  // FP16 only
+    long N;        // elements per component
+};
+
+template <class S>
+struct CField {
+    const typename S::elem* data;
+    const float* scale;
+    long N;
+};
+
+template <class S>
+__host__ __device__ inline CField<S> cfield(Field<S> f) {
+    return {f.data, f.scale, f.N};
+}
+
+template <class S>
+__device__ __forceinline__ void load_spinor(CField<S> f, long i, cx<typename S::real> (&v)[12]) {
+    if constexpr (S::has_scale) {
+        const float sc = f.scale[i];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const float2 t = __half22float2(f.data[c * f.N + i]);
+            v[c] = {t.x * sc, t.y * sc};
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const auto t = f.data[c * f.N + i];
+            v[c] = {t.x, t.y};
+        }
+    }
+}
+
+template <class S>
+__device__ __forceinline__ void store_spinor(Field<S> f, long i, const cx<typename S::real> (&v)[12]) {
+    if constexpr (S::has_scale) {
+        float m = 0.f;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+        const float inv = m > 0.f ? 1.0f / m : 0.f;
+        f.scale[i] = m;
+#pragma unroll
+        for (int c = 0; c < 12; ++c)
+            f.data[c * f.N + i] = __floats2half2_rn(v[c].re * inv, v[c].im * inv);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            typename S::elem t;
+            t.x = v[c].re;
+            t.y = v[c].im;
+            f.data[c * f.N + i] = t;
+        }
+    }
+}
+
+template <class S>
+__device__ __forceinline__ cx<typename S::real> load_link(const typename S::elem* p) {
+    if constexpr (S::has_scale) {
+        const float2 t = __half22float2(*p);
+        return {t.x, t.y};
+    } else {
+        const auto t = *p;
+        return {t.x, t.y};
+    }
+}
+
+// Geometry of one box (see the layout notes above).
+struct Box {
+    int E[4];
+    int off[4];  // origin relative to the domain origin
+    long Vh;     // sites per parity
+};
+
+// Local coordinates of checkerboard site cb of global parity `par` in box b.
+// The domain origin has even global parity (domains start at multiples of
+// even block extents), so the global parity of a local site is
+// (x + y + z + t + sum(off)) mod 2.
+__device__ __forceinline__ void box_coords(const Box& b, long cb, int par, int c[4]) {
+    const int hx = b.E[0] >> 1;
+    long r = cb / hx;
+    const int xh = (int)(cb - r * hx);
+    c[1] = (int)(r % b.E[1]);
+    r /= b.E[1];
+    c[2] = (int)(r % b.E[2]);
+    c[3] = (int)(r / b.E[2]);
+    const int so = b.off[0] + b.off[1] + b.off[2] + b.off[3];
+    c[0] = 2 * xh + ((par + c[1] + c[2] + c[3] + so) & 1);
+}
+
+__device__ __forceinline__ long box_cb(const Box& b, const int c[4]) {
+    return ((((long)c[3] * b.E[2] + c[2]) * b.E[1] + c[1]) * b.E[0] + c[0]) >> 1;
+}
+
+// Dense per-chirality 5D operators are applied as short programs of
+// elementary steps on the s-vector of one (site, component) (see fived.h).
+enum StepKind : int { STEP_NONE = 0, STEP_BIDI = 1, STEP_INV = 2 };
+struct FiveDProg {
+    int nsteps;
+    int kind[3];
+    int dag[3];        // 0: K, 1: K^+
+    double a[3];       // BIDI: 1 + a K ; INV: (1 - a K)^-1
+    double scale[2];   // final scale for upper (spins 0,1) / lower (spins 2,3) chirality
+    int identity;      // 1: program is scale only (no s mixing)
+};
+
+}  // namespace mspcg

@@ -1,0 +1,147 @@
+// Host-side context of the MSPCG library and the operator building blocks
+// shared by apply, the solvers and the force.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/mspcg.h"
+#include "common.h"
+#include "kernels.h"
+
+namespace mspcg {
+
+#define MSPCG_HIP(call)                                  \
+    do {                                                 \
+        if ((call) != hipSuccess) return MSPCG_EHIP;     \
+    } while (0)
+#define MSPCG_TRY(call)              \
+    do {                             \
+        int _e = (call);             \
+        if (_e != 0) return _e < -1 ? MSPCG_EHIP : MSPCG_EUNSUPPORTED; \
+    } while (0)
+
+// Per-kernel-class event timing (only when enabled).
+struct TimingRec {
+    int kc;
+    hipEvent_t a, b;
+    double bytes;
+};
+
+// The five-dimensional programs of the action.
+struct Progs {
+    FiveDProg id, B, Bdag, X, Xdag, M5, M5dag, M5inv, M5invdag;
+};
+
+FiveDProg scaled(FiveDProg p, double s_up, double s_dn);
+
+// Padded block-domain geometry of the local solves.
+struct Domains {
+    int blk[4];
+    int nb[4];
+    int ndom;
+    int pad;
+    Box interior;  // block, offset 0
+    Box pad1;      // block padded by min(pad,1)
+    Box pad2;      // block padded by min(pad,2) (also the link box)
+    long Vh_int;
+    bool built;
+    int prec;      // precision of the links below
+    void* links;   // [ndom][2][8][9][Vh(pad2)]
+};
+
+}  // namespace mspcg
+
+struct mspcg_ctx {
+    mspcg_action act;
+    int device;
+    int L[4];
+    int Ls;
+    long V4, Vh, Nh;  // sites, sites per parity, (site,s) per parity
+    double alpha5, beta5, q5;
+    mspcg::Progs pr;
+    mspcg::Box lat;  // whole lattice box
+    // gauge
+    double2* U;      // boundary-layout copy
+    double2* L64;
+    float2* L32;
+    __half2* L16;
+    bool gauge;
+    // buffers
+    std::map<std::string, std::pair<void*, size_t>> bufs;
+    double* partials;
+    size_t partials_len;
+    mspcg::DevScalars* sc;
+    mspcg::DevScalars* sc_host;  // pinned mirror
+    double* hist;
+    int hist_cap;
+    // blocking
+    mspcg_blocking blocking;
+    bool has_blocking;
+    mspcg::Domains dom;
+    // timing
+    bool timing;
+    std::vector<mspcg::TimingRec> trecs;
+    std::vector<hipEvent_t> evpool;
+    size_t evused;
+
+    void* buf(const std::string& name, size_t bytes);
+};
+
+namespace mspcg {
+
+// Timing scope: records events around the launches of one kernel class.
+struct Timed {
+    mspcg_ctx* c;
+    int kc;
+    double bytes;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(mspcg_ctx* c_, int kc_, double bytes_, hipStream_t st_);
+    ~Timed();
+};
+
+void timing_reset(mspcg_ctx* c);
+void timing_collect(mspcg_ctx* c, mspcg_solve_stats* st);
+
+template <class S>
+Field<S> half_field(mspcg_ctx* c, const std::string& name, long N);
+template <class S>
+typename S::elem* links_of(mspcg_ctx* c);
+
+// Whole-lattice operator pieces on one-parity fields of precision S.
+template <class S>
+int op_hop(mspcg_ctx* c, Field<S> out, CField<S> in, int out_par, bool dag, const FiveDProg& ph,
+           const CField<S>* aux, const FiveDProg& pa, double* partials, const int* done,
+           hipStream_t st);
+template <class S>
+int op_fived(mspcg_ctx* c, Field<S> out, CField<S> in, const FiveDProg& p, double* partials,
+             const int* done, hipStream_t st);
+// y = Mhat p (even); optional |y|^2 partials
+template <class S>
+int op_mhat(mspcg_ctx* c, Field<S> y, CField<S> p, double* partials, const int* done,
+            hipStream_t st);
+template <class S>
+int op_mhatdag(mspcg_ctx* c, Field<S> q, CField<S> y, const int* done, hipStream_t st);
+// q = A p with <p, A p> = |Mhat p|^2 partials
+template <class S>
+int op_A(mspcg_ctx* c, Field<S> q, CField<S> p, double* partials, const int* done,
+         hipStream_t st);
+long hop_nparts(mspcg_ctx* c);
+
+int ensure_partials(mspcg_ctx* c, size_t n);
+
+// Domains of the block preconditioner
+int domains_setup(mspcg_ctx* c, const mspcg_blocking& b, int prec, hipStream_t st);
+template <class S>
+int precond_apply(mspcg_ctx* c, int inner_iters, CField<F64> r_e, Field<F64> z_e,
+                  hipStream_t st, int* inner_done);
+template <class S>
+int kblock_apply(mspcg_ctx* c, CField<F64> p_e, Field<F64> q_e, hipStream_t st);
+
+int solve_one(mspcg_ctx* c, const void* b_dev, void* x_dev, const mspcg_solve_params* p,
+              mspcg_solve_stats* stats, hipStream_t st);
+
+}  // namespace mspcg

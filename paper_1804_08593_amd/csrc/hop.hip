@@ -1,0 +1,315 @@
+// Ls-vectorised Wilson hop with fused fifth-dimension epilogues (gfx950).
+//
+// out(x,s) = Ph[ sum_mu eta (1 -/+ g_mu) U_mu(x) in(x+mu,s) + eta (1 +/- g_mu) U_mu(x-mu)^+ in(x-mu,s) ]
+//          + Pa[ aux(x,s) ]
+// Ph, Pa: 5D programs acting on the s-vector of each site (fived.h); the
+// dagger hop swaps the projector signs.  One thread per (site, s); the
+// workgroup holds whole sites so the s-mixing epilogue runs through LDS.
+//
+// Spin projection in the chiral basis: with g_mu = [[0, e_mu], [e_mu^+, 0]],
+// (1 + sig g_mu) psi = [h ; sig e_mu^+ h] with h = psi_up + sig e_mu psi_dn,
+// so only the 2x3 half spinor h is multiplied by the link.
+//   e_x = -i sigma_x, e_y = -i sigma_y, e_z = -i sigma_z, e_t = 1.
+#include "common.h"
+#include "fived.h"
+#include "kernels.h"
+
+namespace mspcg {
+
+// h = psi_up + sig e_mu psi_dn   (components: spin*3 + colour)
+template <int MU, int SIG, typename T>
+__device__ __forceinline__ void project(const cx<T> (&p)[12], cx<T> (&h)[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cx<T> u0 = p[c], u1 = p[3 + c], d0 = p[6 + c], d1 = p[9 + c];
+        if constexpr (MU == 0) {  // e d = (-i d1, -i d0)
+            h[c] = {u0.re + SIG * d1.im, u0.im - SIG * d1.re};
+            h[3 + c] = {u1.re + SIG * d0.im, u1.im - SIG * d0.re};
+        } else if constexpr (MU == 1) {  // e d = (-d1, d0)
+            h[c] = {u0.re - SIG * d1.re, u0.im - SIG * d1.im};
+            h[3 + c] = {u1.re + SIG * d0.re, u1.im + SIG * d0.im};
+        } else if constexpr (MU == 2) {  // e d = (-i d0, i d1)
+            h[c] = {u0.re + SIG * d0.im, u0.im - SIG * d0.re};
+            h[3 + c] = {u1.re - SIG * d1.im, u1.im + SIG * d1.re};
+        } else {  // e d = d
+            h[c] = {u0.re + SIG * d0.re, u0.im + SIG * d0.im};
+            h[3 + c] = {u1.re + SIG * d1.re, u1.im + SIG * d1.im};
+        }
+    }
+}
+
+// acc_up += w ; acc_dn += sig e_mu^+ w
+template <int MU, int SIG, typename T>
+__device__ __forceinline__ void reconstruct(const cx<T> (&w)[6], cx<T> (&acc)[12]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cx<T> w0 = w[c], w1 = w[3 + c];
+        acc[c].re += w0.re;
+        acc[c].im += w0.im;
+        acc[3 + c].re += w1.re;
+        acc[3 + c].im += w1.im;
+        if constexpr (MU == 0) {  // e^+ w = (i w1, i w0)
+            acc[6 + c].re -= SIG * w1.im;
+            acc[6 + c].im += SIG * w1.re;
+            acc[9 + c].re -= SIG * w0.im;
+            acc[9 + c].im += SIG * w0.re;
+        } else if constexpr (MU == 1) {  // e^+ w = (w1, -w0)
+            acc[6 + c].re += SIG * w1.re;
+            acc[6 + c].im += SIG * w1.im;
+            acc[9 + c].re -= SIG * w0.re;
+            acc[9 + c].im -= SIG * w0.im;
+        } else if constexpr (MU == 2) {  // e^+ w = (i w0, -i w1)
+            acc[6 + c].re -= SIG * w0.im;
+            acc[6 + c].im += SIG * w0.re;
+            acc[9 + c].re += SIG * w1.im;
+            acc[9 + c].im -= SIG * w1.re;
+        } else {  // e^+ w = w
+            acc[6 + c].re += SIG * w0.re;
+            acc[6 + c].im += SIG * w0.im;
+            acc[9 + c].re += SIG * w1.re;
+            acc[9 + c].im += SIG * w1.im;
+        }
+    }
+}
+
+// One direction: acc += (1 + SIG g_mu) L in(nbr)
+template <class S, int MU, int SIG>
+__device__ __forceinline__ void hop_dir(const HopArgs<S>& a, long nbr, const typename S::elem* lk,
+                                        long lstride, cx<typename S::real> (&acc)[12]) {
+    using T = typename S::real;
+    cx<T> p[12];
+    load_spinor<S>(a.in, nbr, p);
+    cx<T> h[6];
+    project<MU, SIG>(p, h);
+    cx<T> u[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u[k] = load_link<S>(lk + k * lstride);
+    cx<T> w[6];
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            cx<T> t = cmul(u[i * 3 + 0], h[sp * 3 + 0]);
+            cfma(t, u[i * 3 + 1], h[sp * 3 + 1]);
+            cfma(t, u[i * 3 + 2], h[sp * 3 + 2]);
+            w[sp * 3 + i] = t;
+        }
+    reconstruct<MU, SIG>(w, acc);
+}
+
+template <int MU, int FWD>
+__device__ __forceinline__ bool neighbour(const HopGeom& g, const int gc[4], long& cb) {
+    int c[4] = {gc[0] - g.in.off[0], gc[1] - g.in.off[1], gc[2] - g.in.off[2], gc[3] - g.in.off[3]};
+    c[MU] += FWD ? 1 : -1;
+    if (g.periodic) {
+        if (c[MU] < 0) c[MU] += g.in.E[MU];
+        if (c[MU] >= g.in.E[MU]) c[MU] -= g.in.E[MU];
+    } else {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            if (c[m] < 0 || c[m] >= g.in.E[m]) return false;
+    }
+    cb = box_cb(g.in, c);
+    return true;
+}
+
+template <class S, int LS>
+__device__ __forceinline__ void block_sum_store(double v, double* dst) {
+    __shared__ double red[16];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) t += red[i];
+        *dst = t;
+    }
+}
+
+// EPI: the epilogue mixes s (needs the LDS exchange); without it no LDS is
+// allocated, which keeps the occupancy of the plain hop high.
+template <class S, int LS, bool DAG, bool EPI>
+__global__ __launch_bounds__(256) void hop_kernel(HopArgs<S> a) {
+    using T = typename S::real;
+    constexpr int SPB = 256 / LS;
+    constexpr int SITE_STRIDE = LS * 12 + 1;  // LDS row padding against bank conflicts
+    __shared__ cx<T> lds[EPI ? SPB * SITE_STRIDE : 1];
+
+    if (a.done && *a.done) return;
+    const int d = blockIdx.y;
+    const int sl = threadIdx.x / LS;
+    const int s = threadIdx.x - sl * LS;
+    const long cb = (long)blockIdx.x * SPB + sl;
+    const bool active = sl < SPB && cb < a.g.out.Vh;
+    const HopGeom& g = a.g;
+
+    cx<T> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
+    int gc[4] = {0, 0, 0, 0};
+    if (active) {
+        int oc[4];
+        box_coords(g.out, cb, g.out_par, oc);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) gc[m] = oc[m] + g.out.off[m];
+        int lc[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) lc[m] = gc[m] - g.link.off[m];
+        const long lcb = box_cb(g.link, lc);
+        const long lstride = g.link.Vh;
+        const typename S::elem* lbase =
+            a.links + (long)d * a.link_dom_stride + (long)g.out_par * 8 * 9 * lstride + lcb;
+        const long ibase = (long)d * g.in.Vh;
+        // forward terms use (1 - g) and backward (1 + g); the dagger swaps them
+        constexpr int SF = DAG ? 1 : -1;
+        constexpr int SB = -SF;
+        long n;
+#define MSPCG_DIR(MU)                                                                     \
+    if (neighbour<MU, 1>(g, gc, n))                                                        \
+        hop_dir<S, MU, SF>(a, (ibase + n) * LS + s, lbase + (MU)*9 * lstride, lstride, acc); \
+    if (neighbour<MU, 0>(g, gc, n))                                                        \
+        hop_dir<S, MU, SB>(a, (ibase + n) * LS + s, lbase + (4 + (MU)) * 9 * lstride, lstride, acc);
+        MSPCG_DIR(0)
+        MSPCG_DIR(1)
+        MSPCG_DIR(2)
+        MSPCG_DIR(3)
+#undef MSPCG_DIR
+    }
+
+    const long oidx = ((long)d * g.out.Vh + cb) * LS + s;
+    cx<T> res[12];
+    const T mf = (T)a.mf;
+    if (!EPI || a.ph.identity) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const T sc = (T)(c < 6 ? a.ph.scale[0] : a.ph.scale[1]);
+            res[c] = {acc[c].re * sc, acc[c].im * sc};
+        }
+    } else {
+        if (active) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) lds[sl * SITE_STRIDE + s * 12 + c] = acc[c];
+        }
+        __syncthreads();
+        for (int ch = threadIdx.x; ch < SPB * 12; ch += blockDim.x) {
+            const int csl = ch / 12, comp = ch - csl * 12;
+            cx<T> v[LS];
+#pragma unroll
+            for (int t = 0; t < LS; ++t) v[t] = lds[csl * SITE_STRIDE + t * 12 + comp];
+            apply_prog<LS, T>(a.ph, comp < 6, mf, v);
+#pragma unroll
+            for (int t = 0; t < LS; ++t) lds[csl * SITE_STRIDE + t * 12 + comp] = v[t];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 12; ++c) res[c] = lds[sl * SITE_STRIDE + s * 12 + c];
+    }
+
+    if (a.has_aux) {
+        // aux lives on its own box; sites outside it contribute zero
+        cx<T> x[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) x[c] = {0, 0};
+        if (active) {
+            int ac[4];
+            bool in = true;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                ac[m] = gc[m] - g.aux.off[m];
+                in = in && ac[m] >= 0 && ac[m] < g.aux.E[m];
+            }
+            if (in) load_spinor<S>(a.aux, ((long)d * g.aux.Vh + box_cb(g.aux, ac)) * LS + s, x);
+        }
+        if (!EPI || a.pa.identity) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const T sc = (T)(c < 6 ? a.pa.scale[0] : a.pa.scale[1]);
+                res[c].re += sc * x[c].re;
+                res[c].im += sc * x[c].im;
+            }
+        } else {
+            __syncthreads();  // the hop epilogue may still read lds
+            if (active) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) lds[sl * SITE_STRIDE + s * 12 + c] = x[c];
+            }
+            __syncthreads();
+            for (int ch = threadIdx.x; ch < SPB * 12; ch += blockDim.x) {
+                const int csl = ch / 12, comp = ch - csl * 12;
+                cx<T> v[LS];
+#pragma unroll
+                for (int t = 0; t < LS; ++t) v[t] = lds[csl * SITE_STRIDE + t * 12 + comp];
+                apply_prog<LS, T>(a.pa, comp < 6, mf, v);
+#pragma unroll
+                for (int t = 0; t < LS; ++t) lds[csl * SITE_STRIDE + t * 12 + comp] = v[t];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const cx<T> t = lds[sl * SITE_STRIDE + s * 12 + c];
+                res[c].re += t.re;
+                res[c].im += t.im;
+            }
+        }
+    }
+
+    if (active) store_spinor<S>(a.out, oidx, res);
+    if (a.partials) {
+        double n2 = 0;
+        if (active) {
+            // norm of what was stored (FP16 rounding included is not needed:
+            // the reduction uses the arithmetic value)
+#pragma unroll
+            for (int c = 0; c < 12; ++c) n2 += (double)res[c].re * res[c].re + (double)res[c].im * res[c].im;
+        }
+        block_sum_store<S, LS>(n2, a.partials + (long)d * gridDim.x + blockIdx.x);
+    }
+}
+
+template <class S, int LS>
+static void launch_ls(const HopArgs<S>& a, int ndom, bool dag, hipStream_t st) {
+    constexpr int SPB = 256 / LS;
+    dim3 grid((unsigned)((a.g.out.Vh + SPB - 1) / SPB), (unsigned)ndom);
+    dim3 block(SPB * LS);
+    const bool epi = !a.ph.identity || (a.has_aux && !a.pa.identity);
+    if (dag) {
+        if (epi)
+            hipLaunchKernelGGL((hop_kernel<S, LS, true, true>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((hop_kernel<S, LS, true, false>), grid, block, 0, st, a);
+    } else {
+        if (epi)
+            hipLaunchKernelGGL((hop_kernel<S, LS, false, true>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((hop_kernel<S, LS, false, false>), grid, block, 0, st, a);
+    }
+}
+
+template <class S>
+int launch_hop(const HopArgs<S>& a, int Ls, int ndom, bool dag, hipStream_t st) {
+    switch (Ls) {
+#define MSPCG_CASE(L) \
+    case L: launch_ls<S, L>(a, ndom, dag, st); break;
+        MSPCG_LS_LIST(MSPCG_CASE)
+#undef MSPCG_CASE
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template <class S>
+long hop_grid_x(long Vh, int Ls) {
+    const int spb = 256 / Ls;
+    return (Vh + spb - 1) / spb;
+}
+
+template int launch_hop<F64>(const HopArgs<F64>&, int, int, bool, hipStream_t);
+template int launch_hop<F32>(const HopArgs<F32>&, int, int, bool, hipStream_t);
+template int launch_hop<F16>(const HopArgs<F16>&, int, int, bool, hipStream_t);
+template long hop_grid_x<F64>(long, int);
+template long hop_grid_x<F32>(long, int);
+template long hop_grid_x<F16>(long, int);
+
+}  // namespace mspcg

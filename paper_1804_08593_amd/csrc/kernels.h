@@ -1,0 +1,128 @@
+// Kernel argument structures and host-side launchers of the MSPCG library.
+#pragma once
+#include "common.h"
+
+// Fifth-dimension extents compiled into the kernels.
+#define MSPCG_LS_LIST(X) X(2) X(4) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32)
+
+namespace mspcg {
+
+// Geometry of one hop launch: every domain has an output box, an input box,
+// an aux box and a link box (all relative to the domain origin).  The
+// periodic (whole-lattice) case has one domain and four identical boxes.
+struct HopGeom {
+    Box out, in, aux, link;
+    int out_par;   // global parity of the output sites
+    int periodic;  // 1: wrap at the input-box edges (whole lattice); 0: drop hops leaving it
+};
+
+template <class S>
+struct HopArgs {
+    CField<S> in;
+    Field<S> out;
+    CField<S> aux;
+    const typename S::elem* links;
+    long link_dom_stride;  // elements between the link arrays of consecutive domains
+    HopGeom g;
+    FiveDProg ph;  // applied to the hop result
+    FiveDProg pa;  // applied to aux
+    int has_aux;
+    double mf;
+    double* partials;  // optional: per (domain, workgroup) sum |out|^2
+    const int* done;   // optional: skip the launch when *done != 0
+};
+
+template <class S>
+int launch_hop(const HopArgs<S>& a, int Ls, int ndom, bool dag, hipStream_t st);
+template <class S>
+long hop_grid_x(long Vh, int Ls);
+
+// out = P(in) on one box per domain (optionally |out|^2 partials).
+template <class S>
+struct FiveDArgs {
+    CField<S> in;
+    Field<S> out;
+    long Vh;  // sites per domain
+    FiveDProg p;
+    double mf;
+    double* partials;
+    const int* done;
+};
+template <class S>
+int launch_fived(const FiveDArgs<S>& a, int Ls, int ndom, hipStream_t st);
+long fived_grid_x(long Vh, int Ls);
+
+// ---- layout conversion -------------------------------------------------
+// boundary full field complex128 [Ls][Lt][Lz][Ly][Lx][4][3] <-> one parity of
+// the internal whole-lattice layout.
+template <class S>
+int launch_pack_parity(const double2* full, Field<S> out, const int dims[4], int Ls, int par,
+                       hipStream_t st);
+template <class S>
+int launch_unpack_parity(CField<S> in, double2* full, const int dims[4], int Ls, int par,
+                         int zero_other, hipStream_t st);
+
+// internal whole-lattice parity field <-> per-domain interior fields.  The
+// domain grid is nb[4] blocks of extent blk[4]; domain d's origin is at
+// blk * (d decomposed x-fastest).
+template <class SG, class SD>
+int launch_global_to_domain(CField<SG> g, Field<SD> dom, const int dims[4], const int blk[4],
+                            const int nb[4], int Ls, int par, hipStream_t st);
+template <class SD, class SG>
+int launch_domain_to_global(CField<SD> dom, Field<SG> g, const int dims[4], const int blk[4],
+                            const int nb[4], int Ls, int par, hipStream_t st);
+
+// Links for the link box of every domain (whole lattice: one domain, pad 0).
+// U: boundary complex128 [4][Lt][Lz][Ly][Lx][3][3].
+template <class S>
+int launch_pack_links(const double2* U, typename S::elem* out, const int dims[4], const int blk[4],
+                      const int nb[4], const Box& linkbox, int antiperiodic_t, hipStream_t st);
+
+// ---- BLAS-1 and reductions ---------------------------------------------
+// All vector kernels work on N = ndom*Vh*Ls elements per component; a 2D
+// grid (x: chunks within a domain, y: domain) gives per-domain partial sums.
+long blas_grid_x(long per_dom);
+
+// Scalars of one solve, kept on the device.
+struct DevScalars {
+    double rr;       // current |r|^2 (iterated)
+    double pq;       // <p, A p>
+    double alpha;
+    double beta;
+    double zr;       // <z, r>   (flexible PCG)
+    double zq;       // <z_new, q>
+    double tol2;     // tol^2 |b|^2
+    double bb;       // |b|^2
+    int done;        // iterated residual reached tol2
+    int iter;        // iterations done
+    int breakdown;   // non-positive curvature or NaN
+};
+
+int launch_reduce_sum(const double* partials, int nparts, double* out, hipStream_t st);
+// per-domain sums: partials [ndom][nparts] -> out[ndom]
+int launch_reduce_domains(const double* partials, int ndom, int nparts, double* out,
+                          hipStream_t st);
+
+// CG scalar updates (single thread kernels)
+int launch_cg_alpha(DevScalars* sc, const double* partials, int nparts, hipStream_t st);
+int launch_cg_beta(DevScalars* sc, const double* partials, int nparts, double* hist,
+                   int hist_cap, hipStream_t st);
+
+// FP64 whole-lattice vector kernels
+int launch_cg_update_xr(double2* x, double2* r, const double2* p, const double2* q, long N,
+                        const DevScalars* sc, double* partials, long nparts, hipStream_t st);
+int launch_xpay(double2* p, const double2* r, long N, const DevScalars* sc, int which,
+                hipStream_t st);
+int launch_sub_norm(double2* r, const double2* b, const double2* ax, long N, double* partials,
+                    long nparts, hipStream_t st);
+int launch_copy_norm(double2* dst, const double2* src, long N, double* partials, long nparts,
+                     hipStream_t st);
+int launch_dot2(const double2* z, const double2* r, const double2* q, long N, double* partials,
+                long nparts, hipStream_t st);
+int launch_axpy(double2* y, const double2* x, double a, long N, hipStream_t st);
+
+// Mixed-precision conversions (whole vectors)
+template <class SI, class SO>
+int launch_convert(CField<SI> in, Field<SO> out, long n_sites, hipStream_t st);
+
+}  // namespace mspcg

@@ -1,0 +1,242 @@
+"""Thin ctypes binding of libmspcg.so (include/mspcg.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch supplies device memory (complex128 CUDA tensors) and the current
+stream.  The library must be built (paper_1804_08593_amd.build); there is no
+CPU fallback, and loading fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmspcg.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOGAUGE, ENOCONV, EBREAKDOWN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+OP_D, OP_DDAG, OP_HOP, OP_HOPDAG, OP_MHAT, OP_MHATDAG, OP_A, OP_M5INV, OP_PREPARE, OP_KBLOCK = range(10)
+FP64, FP32, FP16 = 0, 1, 2
+SOLVER_CG, SOLVER_MIXED_CG, SOLVER_MSPCG = 0, 1, 2
+KC_HOP64, KC_HOP32, KC_HOPDOM, KC_FIVED, KC_BLAS = range(5)
+KC_NAMES = ("hop64", "hop32", "hopdom", "fived", "blas")
+KC_COUNT = 5
+EXPORTS = ("mspcg_create", "mspcg_destroy", "mspcg_strerror", "mspcg_version",
+           "mspcg_load_gauge", "mspcg_apply", "mspcg_set_blocking", "mspcg_precond",
+           "mspcg_solve", "mspcg_solve_batch", "mspcg_force")
+
+
+class MspcgError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+class Action(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int * 4), ("Ls", ctypes.c_int), ("M5", ctypes.c_double),
+                ("mf", ctypes.c_double), ("b", ctypes.c_double), ("c", ctypes.c_double),
+                ("antiperiodic_t", ctypes.c_int)]
+
+
+class Blocking(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int * 4), ("pad", ctypes.c_int)]
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("solver", ctypes.c_int),
+                ("use_x0", ctypes.c_int), ("blocking", Blocking), ("inner_iters", ctypes.c_int),
+                ("inner_prec", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("delta", ctypes.c_double), ("timing", ctypes.c_int)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int), ("inner_iters_total", ctypes.c_int),
+                ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
+                ("true_rel_resid", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("resid_history", ctypes.POINTER(ctypes.c_double)),
+                ("resid_history_cap", ctypes.c_int), ("resid_history_len", ctypes.c_int),
+                ("kernel_ms", ctypes.c_double * KC_COUNT),
+                ("kernel_launches", ctypes.c_long * KC_COUNT),
+                ("kernel_bytes", ctypes.c_double * KC_COUNT)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libmspcg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with "
+                              "`python -m paper_1804_08593_amd.build` (no CPU fallback exists)")
+        try:  # share torch's HIP runtime (same soname) when torch is present
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        lib = ctypes.CDLL(path)
+        P, I = ctypes.c_void_p, ctypes.c_int
+        lib.mspcg_create.argtypes = [ctypes.POINTER(Action), I, ctypes.POINTER(P)]
+        lib.mspcg_destroy.argtypes = [P]
+        lib.mspcg_destroy.restype = None
+        lib.mspcg_strerror.argtypes = [I]
+        lib.mspcg_strerror.restype = ctypes.c_char_p
+        lib.mspcg_version.restype = I
+        lib.mspcg_load_gauge.argtypes = [P, P, P]
+        lib.mspcg_apply.argtypes = [P, I, I, P, P, P]
+        lib.mspcg_set_blocking.argtypes = [P, ctypes.POINTER(Blocking)]
+        lib.mspcg_precond.argtypes = [P, I, I, P, P, P]
+        lib.mspcg_solve.argtypes = [P, P, P, ctypes.POINTER(SolveParams),
+                                    ctypes.POINTER(SolveStats), P]
+        lib.mspcg_solve_batch.argtypes = [ctypes.POINTER(P), I, ctypes.POINTER(P),
+                                          ctypes.POINTER(P), ctypes.POINTER(SolveParams),
+                                          ctypes.POINTER(SolveStats), P]
+        lib.mspcg_force.argtypes = [P, P, P, P, P]
+        _lib = lib
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return load().mspcg_strerror(int(code)).decode()
+
+
+def _check(code: int, where: str, allow=()):
+    if code != OK and code not in allow:
+        raise MspcgError(code, where)
+    return code
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    import torch
+    assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128, \
+        "fields are complex128 CUDA tensors"
+    assert t.is_contiguous()
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_params(tol=1e-10, maxiter=10000, solver=SOLVER_CG, use_x0=False, block=(0, 0, 0, 0),
+                pad=2, inner_iters=6, inner_prec=FP16, check_every=0, delta=0.1,
+                timing=False) -> SolveParams:
+    p = SolveParams()
+    p.tol, p.maxiter, p.solver, p.use_x0 = float(tol), int(maxiter), int(solver), int(use_x0)
+    for i in range(4):
+        p.blocking.block[i] = int(block[i])
+    p.blocking.pad = int(pad)
+    p.inner_iters, p.inner_prec = int(inner_iters), int(inner_prec)
+    p.check_every, p.delta, p.timing = int(check_every), float(delta), int(timing)
+    return p
+
+
+class Context:
+    """One action on one device (mspcg_ctx)."""
+
+    def __init__(self, dims, Ls, M5, mf, b=1.0, c=0.0, antiperiodic_t=True, device=0):
+        lib = load()
+        a = Action()
+        for i in range(4):
+            a.dims[i] = int(dims[i])
+        a.Ls, a.M5, a.mf, a.b, a.c = int(Ls), float(M5), float(mf), float(b), float(c)
+        a.antiperiodic_t = int(bool(antiperiodic_t))
+        h = ctypes.c_void_p()
+        _check(lib.mspcg_create(ctypes.byref(a), int(device), ctypes.byref(h)), "mspcg_create")
+        self._h = h
+        self.dims = tuple(int(x) for x in dims)
+        self.Ls = int(Ls)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().mspcg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def fshape(self):
+        Lx, Ly, Lz, Lt = self.dims
+        return (self.Ls, Lt, Lz, Ly, Lx, 4, 3)
+
+    @property
+    def gshape(self):
+        Lx, Ly, Lz, Lt = self.dims
+        return (4, Lt, Lz, Ly, Lx, 3, 3)
+
+    def load_gauge(self, U, stream=None):
+        _check(load().mspcg_load_gauge(self._h, _ptr(U), _stream(stream)), "mspcg_load_gauge")
+
+    def apply(self, op, inp, out, prec=FP64, stream=None):
+        _check(load().mspcg_apply(self._h, int(op), int(prec), _ptr(inp), _ptr(out),
+                                  _stream(stream)), "mspcg_apply")
+        return out
+
+    def set_blocking(self, block, pad=2):
+        b = Blocking()
+        for i in range(4):
+            b.block[i] = int(block[i])
+        b.pad = int(pad)
+        _check(load().mspcg_set_blocking(self._h, ctypes.byref(b)), "mspcg_set_blocking")
+
+    def precond(self, r, z, inner_iters, prec=FP16, stream=None):
+        _check(load().mspcg_precond(self._h, int(inner_iters), int(prec), _ptr(r), _ptr(z),
+                                    _stream(stream)), "mspcg_precond")
+        return z
+
+    def solve(self, b, x, params: SolveParams, history=0, stream=None, allow_noconv=False):
+        st = SolveStats()
+        hist = None
+        if history:
+            hist = (ctypes.c_double * int(history))()
+            st.resid_history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+            st.resid_history_cap = int(history)
+        rc = load().mspcg_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(params),
+                                ctypes.byref(st), _stream(stream))
+        _check(rc, "mspcg_solve", allow=(ENOCONV,) if allow_noconv else ())
+        return stats_dict(st, hist, rc)
+
+    def force(self, X, Y, F, stream=None):
+        _check(load().mspcg_force(self._h, _ptr(X), _ptr(Y), _ptr(F), _stream(stream)),
+               "mspcg_force")
+        return F
+
+
+def stats_dict(st: SolveStats, hist=None, rc=OK) -> dict:
+    d = {
+        "rc": rc,
+        "outer_iters": st.outer_iters,
+        "inner_iters_total": st.inner_iters_total,
+        "restarts": st.restarts,
+        "converged": bool(st.converged),
+        "true_rel_resid": st.true_rel_resid,
+        "seconds": st.seconds,
+        "kernel_ms": {KC_NAMES[i]: st.kernel_ms[i] for i in range(KC_COUNT)},
+        "kernel_launches": {KC_NAMES[i]: int(st.kernel_launches[i]) for i in range(KC_COUNT)},
+        "kernel_bytes": {KC_NAMES[i]: st.kernel_bytes[i] for i in range(KC_COUNT)},
+    }
+    if hist is not None:
+        d["history"] = np.array(hist[:st.resid_history_len])
+    return d
+
+
+def solve_batch(ctxs, bs, xs, params: SolveParams, stream=None):
+    n = len(ctxs)
+    H = (ctypes.c_void_p * n)(*[c.handle for c in ctxs])
+    B = (ctypes.c_void_p * n)(*[_ptr(b) for b in bs])
+    X = (ctypes.c_void_p * n)(*[_ptr(x) for x in xs])
+    sts = (SolveStats * n)()
+    rc = load().mspcg_solve_batch(H, n, B, X, ctypes.byref(params), sts, _stream(stream))
+    _check(rc, "mspcg_solve_batch")
+    return [stats_dict(sts[i]) for i in range(n)]

@@ -1,0 +1,70 @@
+"""The C-ABI library loads, exports every symbol include/mspcg.h declares, and
+validates arguments on the host (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1804_08593_amd import mspcg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mspcg.h")).read()
+    return sorted(set(re.findall(r"\b(mspcg_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = mspcg.load()
+    names = _declared()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(mspcg.EXPORTS) == set(names)
+    assert lib.mspcg_version() == 1
+
+
+def test_strerror_texts():
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert mspcg.strerror(code)
+    assert mspcg.strerror(-99) == "unknown error"
+
+
+@pytest.mark.parametrize("dims,Ls,err", [
+    ((3, 4, 4, 4), 8, mspcg.EINVAL),      # odd extent
+    ((4, 4, 4, 0), 8, mspcg.EINVAL),      # empty lattice
+    ((4, 4, 4, 4), 1, mspcg.EINVAL),      # Ls < 2
+    ((4, 4, 4, 4), 7, mspcg.EUNSUPPORTED),  # Ls not compiled in
+])
+def test_create_rejects_bad_actions(dims, Ls, err):
+    lib = mspcg.load()
+    a = mspcg.Action()
+    for i in range(4):
+        a.dims[i] = dims[i]
+    a.Ls, a.M5, a.mf, a.b, a.c, a.antiperiodic_t = Ls, 1.8, 0.1, 1.0, 0.0, 1
+    h = ctypes.c_void_p()
+    assert lib.mspcg_create(ctypes.byref(a), 0, ctypes.byref(h)) == err
+    assert not h.value
+
+
+def test_create_rejects_bad_parameters():
+    lib = mspcg.load()
+    for b, c, mf in [(0.0, 0.5, 0.1), (float("nan"), 0.0, 0.1), (1.0, 0.0, float("inf"))]:
+        a = mspcg.Action()
+        for i in range(4):
+            a.dims[i] = 4
+        a.Ls, a.M5, a.mf, a.b, a.c, a.antiperiodic_t = 8, 1.8, mf, b, c, 1
+        h = ctypes.c_void_p()
+        assert lib.mspcg_create(ctypes.byref(a), 0, ctypes.byref(h)) == mspcg.EINVAL
+
+
+def test_null_pointers_rejected():
+    lib = mspcg.load()
+    assert lib.mspcg_create(None, 0, None) == mspcg.EINVAL
+    assert lib.mspcg_apply(None, 0, 0, None, None, None) == mspcg.EINVAL
+    assert lib.mspcg_solve(None, None, None, None, None, None) == mspcg.EINVAL
+    assert lib.mspcg_force(None, None, None, None, None) == mspcg.EINVAL
+    assert lib.mspcg_load_gauge(None, None, None) == mspcg.EINVAL
+    lib.mspcg_destroy(None)
