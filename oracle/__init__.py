@@ -418,6 +418,7 @@ def mspcg(act: Action, U, bhat, block, l: int, tol=1e-10, maxiter=10000, x0=None
         info.iters = k
         rel = np.sqrt(norm2(r_new)) / bnorm
         info.history.append(rel)
+        restart = False
         if rel <= tol:
             rt = bhat - A(x)
             tr = np.sqrt(norm2(rt)) / bnorm
@@ -425,8 +426,10 @@ def mspcg(act: Action, U, bhat, block, l: int, tol=1e-10, maxiter=10000, x0=None
                 info.converged, info.true_rel_resid = True, tr
                 return x, info
             r_new = rt
+            restart = True
         z_new = K(r_new)
-        beta = dot(z_new, r_new - r).real / zr
+        # a replaced residual restarts the recurrence (p = z)
+        beta = 0.0 if restart else dot(z_new, r_new - r).real / zr
         zr = dot(z_new, r_new).real
         p = z_new + beta * p
         r = r_new

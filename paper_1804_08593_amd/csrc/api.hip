@@ -162,7 +162,7 @@ int op_hop(mspcg_ctx* c, Field<S> out, CField<S> in, int out_par, bool dag, cons
     a.link_dom_stride = 0;
     a.g.out = a.g.in = a.g.aux = a.g.link = c->lat;
     a.g.out_par = out_par;
-    a.g.periodic = 1;
+    a.g.periodic = 0xF;
     a.ph = ph;
     a.pa = pa;
     a.has_aux = aux != nullptr;

@@ -99,7 +99,8 @@ __device__ double block_sum_all(const double* p, int n) {
     return r;
 }
 
-__global__ void cg_alpha_kernel(DevScalars* sc, const double* partials, int nparts) {
+// alpha = rr / <p, A p> (CG) or <z, r> / <p, A p> (flexible PCG)
+__global__ void cg_alpha_kernel(DevScalars* sc, const double* partials, int nparts, int flexible) {
     if (sc->done) return;
     const double pq = block_sum_all(partials, nparts);
     if (threadIdx.x == 0) {
@@ -109,7 +110,24 @@ __global__ void cg_alpha_kernel(DevScalars* sc, const double* partials, int npar
             sc->done = 1;
             sc->alpha = 0.0;
         } else {
-            sc->alpha = sc->rr / pq;
+            sc->alpha = (flexible ? sc->zr : sc->rr) / pq;
+        }
+    }
+}
+
+// Flexible (Polak-Ribiere) beta from <z_new, r_new> and <z_new, q>:
+// r_old = r_new + alpha q, so <z_new, r_new - r_old> = -alpha <z_new, q>.
+__global__ void fpcg_beta_kernel(DevScalars* sc, const double* partials, int nparts) {
+    if (sc->done) return;
+    const double zr = block_sum_all(partials, nparts);
+    const double zq = block_sum_all(partials + nparts, nparts);
+    if (threadIdx.x == 0) {
+        sc->beta = sc->zr != 0.0 ? -sc->alpha * zq / sc->zr : 0.0;
+        sc->zr = zr;
+        sc->zq = zq;
+        if (!(zr > 0.0) || !isfinite(zr)) {
+            sc->breakdown = 1;
+            sc->done = 1;
         }
     }
 }
@@ -218,9 +236,75 @@ __global__ void axpy_kernel(double2* y, const double2* x, double a, long n) {
     }
 }
 
+// FP32 variants of the CG vector updates (double accumulation of norms)
+__global__ void cg_update_xr32_kernel(float2* x, float2* r, const float2* p, const float2* q,
+                                      long n, const DevScalars* sc, double* partials) {
+    if (sc->done) return;
+    const float al = (float)sc->alpha;
+    double acc = 0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        const float2 pv = p[i], qv = q[i];
+        float2 xv = x[i], rv = r[i];
+        xv.x += al * pv.x;
+        xv.y += al * pv.y;
+        rv.x -= al * qv.x;
+        rv.y -= al * qv.y;
+        x[i] = xv;
+        r[i] = rv;
+        acc += (double)rv.x * rv.x + (double)rv.y * rv.y;
+    }
+    block_reduce_store(acc, partials + blockIdx.x);
+}
+
+__global__ void xpay32_kernel(float2* p, const float2* r, long n, const DevScalars* sc) {
+    if (sc->done) return;
+    const float b = (float)sc->beta;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        const float2 rv = r[i];
+        float2 pv = p[i];
+        pv.x = rv.x + b * pv.x;
+        pv.y = rv.y + b * pv.y;
+        p[i] = pv;
+    }
+}
+
+// x (FP64) += xs (FP32); xs = 0
+__global__ void accum32_kernel(double2* x, float2* xs, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        const float2 v = xs[i];
+        double2 xv = x[i];
+        xv.x += (double)v.x;
+        xv.y += (double)v.y;
+        x[i] = xv;
+        xs[i] = make_float2(0.f, 0.f);
+    }
+}
+
 int last_error() { return hipGetLastError() == hipSuccess ? 0 : -2; }
 
 }  // namespace
+
+int launch_cg_update_xr32(float2* x, float2* r, const float2* p, const float2* q, long N,
+                          const DevScalars* sc, double* partials, long nparts, hipStream_t st) {
+    hipLaunchKernelGGL(cg_update_xr32_kernel, dim3((unsigned)nparts), dim3(kThreads), 0, st, x, r,
+                       p, q, 12 * N, sc, partials);
+    return last_error();
+}
+
+int launch_xpay32(float2* p, const float2* r, long N, const DevScalars* sc, hipStream_t st) {
+    hipLaunchKernelGGL(xpay32_kernel, dim3((unsigned)blas_grid_x(12 * N)), dim3(kThreads), 0, st,
+                       p, r, 12 * N, sc);
+    return last_error();
+}
+
+int launch_accum32(double2* x, float2* xs, long N, hipStream_t st) {
+    hipLaunchKernelGGL(accum32_kernel, dim3((unsigned)blas_grid_x(12 * N)), dim3(kThreads), 0, st,
+                       x, xs, 12 * N);
+    return last_error();
+}
 
 template <class S>
 int launch_fived(const FiveDArgs<S>& a, int Ls, int ndom, hipStream_t st) {
@@ -260,8 +344,15 @@ int launch_reduce_domains(const double* partials, int ndom, int nparts, double* 
     return last_error();
 }
 
-int launch_cg_alpha(DevScalars* sc, const double* partials, int nparts, hipStream_t st) {
-    hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(kThreads), 0, st, sc, partials, nparts);
+int launch_cg_alpha(DevScalars* sc, const double* partials, int nparts, hipStream_t st,
+                    int flexible) {
+    hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(kThreads), 0, st, sc, partials, nparts,
+                       flexible);
+    return last_error();
+}
+
+int launch_fpcg_beta(DevScalars* sc, const double* partials, int nparts, hipStream_t st) {
+    hipLaunchKernelGGL(fpcg_beta_kernel, dim3(1), dim3(kThreads), 0, st, sc, partials, nparts);
     return last_error();
 }
 

@@ -135,9 +135,13 @@ int ensure_partials(mspcg_ctx* c, size_t n);
 
 // Domains of the block preconditioner
 int domains_setup(mspcg_ctx* c, const mspcg_blocking& b, int prec, hipStream_t st);
+size_t precond_partials_need(mspcg_ctx* c);
 template <class S>
 int precond_apply(mspcg_ctx* c, int inner_iters, CField<F64> r_e, Field<F64> z_e,
                   hipStream_t st, int* inner_done);
+template <class S>
+int precond_apply_flag(mspcg_ctx* c, int l, CField<F64> r, Field<F64> z, const int* done,
+                       hipStream_t st);
 template <class S>
 int kblock_apply(mspcg_ctx* c, CField<F64> p_e, Field<F64> q_e, hipStream_t st);
 

@@ -101,14 +101,15 @@ template <int MU, int FWD>
 __device__ __forceinline__ bool neighbour(const HopGeom& g, const int gc[4], long& cb) {
     int c[4] = {gc[0] - g.in.off[0], gc[1] - g.in.off[1], gc[2] - g.in.off[2], gc[3] - g.in.off[3]};
     c[MU] += FWD ? 1 : -1;
-    if (g.periodic) {
+    // directions in the periodic mask wrap (the box spans the lattice there);
+    // all others drop hops whose source lies outside the input box
+    if ((g.periodic >> MU) & 1) {
         if (c[MU] < 0) c[MU] += g.in.E[MU];
         if (c[MU] >= g.in.E[MU]) c[MU] -= g.in.E[MU];
-    } else {
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-            if (c[m] < 0 || c[m] >= g.in.E[m]) return false;
     }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        if (!((g.periodic >> m) & 1) && (c[m] < 0 || c[m] >= g.in.E[m])) return false;
     cb = box_cb(g.in, c);
     return true;
 }

@@ -13,7 +13,8 @@ namespace mspcg {
 struct HopGeom {
     Box out, in, aux, link;
     int out_par;   // global parity of the output sites
-    int periodic;  // 1: wrap at the input-box edges (whole lattice); 0: drop hops leaving it
+    int periodic;  // bit mu set: wrap at the input-box edges in direction mu (the
+                   // box spans the lattice there); clear: drop hops leaving the box
 };
 
 template <class S>
@@ -104,7 +105,9 @@ int launch_reduce_domains(const double* partials, int ndom, int nparts, double* 
                           hipStream_t st);
 
 // CG scalar updates (single thread kernels)
-int launch_cg_alpha(DevScalars* sc, const double* partials, int nparts, hipStream_t st);
+int launch_cg_alpha(DevScalars* sc, const double* partials, int nparts, hipStream_t st,
+                    int flexible = 0);
+int launch_fpcg_beta(DevScalars* sc, const double* partials, int nparts, hipStream_t st);
 int launch_cg_beta(DevScalars* sc, const double* partials, int nparts, double* hist,
                    int hist_cap, hipStream_t st);
 
@@ -120,6 +123,12 @@ int launch_copy_norm(double2* dst, const double2* src, long N, double* partials,
 int launch_dot2(const double2* z, const double2* r, const double2* q, long N, double* partials,
                 long nparts, hipStream_t st);
 int launch_axpy(double2* y, const double2* x, double a, long N, hipStream_t st);
+
+// FP32 iterations of the mixed-precision CG
+int launch_cg_update_xr32(float2* x, float2* r, const float2* p, const float2* q, long N,
+                          const DevScalars* sc, double* partials, long nparts, hipStream_t st);
+int launch_xpay32(float2* p, const float2* r, long N, const DevScalars* sc, hipStream_t st);
+int launch_accum32(double2* x, float2* xs, long N, hipStream_t st);
 
 // Mixed-precision conversions (whole vectors)
 template <class SI, class SO>

@@ -1,28 +1,494 @@
-// Block preconditioner of Sec. 2.3 (eqs. (4)-(5), Fig. 3) -- placeholder
-// until the padded-domain operator lands.
+// The multisplitting preconditioner of Sec. 2.3 (eqs. (4)-(5), Fig. 3).
+//
+// K = (+)_s A_s with A_s = P_s A P_s: the diagonal block of A = Mhat^+ Mhat
+// for block s, every entry coupling two different blocks set to zero.  A
+// applied to a field supported on block s reaches at most two sites beyond
+// the block (Mhat hops e -> o -> e), and only paths that return into the
+// block survive the final projection, so
+//     A_s p_s = P_s Mhat_D^+ Mhat_D p_s
+// exactly, where Mhat_D is the Schur operator on the block padded by two
+// sites (the "domain") with every hop leaving the domain dropped.  Each stage
+// of Mhat_D^+ Mhat_D is evaluated only on the part of the domain that can
+// still contribute (odd sites within one site of the block, even sites
+// within two), i.e. the four hops run on boxes padded by 1, 2, 1 and 0.
+// A block that spans a whole lattice direction wraps periodically there.
+// pad = 0 gives the cheaper Dirichlet-cut block operator Mhat_s^+ Mhat_s.
+//
+// K_l^-1 r: l CG iterations per block from a zero guess (eq. (4)), all blocks
+// in one launch per step, with per-block scalars; storage precision S (FP16
+// with per-(x,s) scales, FP32 or FP64), arithmetic in FP32 (FP64 for F64).
+#include <string.h>
+
 #include "ctx.h"
+#include "fived.h"
 
 namespace mspcg {
 
-int domains_setup(mspcg_ctx*, const mspcg_blocking&, int, hipStream_t) {
-    return MSPCG_EUNSUPPORTED;
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ void block_reduce_store(double v, double* dst) {
+    __shared__ double red[kThreads / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) t += red[i];
+        *dst = t;
+    }
+}
+
+// per-domain scalars of the local CG
+struct InnerScalars {
+    double* gam;   // <rho, rho>
+    double* a;     // step length
+    double* beta;
+    int* active;
+};
+
+// one workgroup per domain: fixed-order sum of that domain's partials
+__device__ double domain_sum(const double* p, int n) {
+    __shared__ double red2[kThreads];
+    double v = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
+    red2[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red2[threadIdx.x] += red2[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double r = red2[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ void inner_start_scalars(InnerScalars s, const double* partials, int np,
+                                    const int* done) {
+    if (done && *done) return;
+    const int d = blockIdx.x;
+    const double g = domain_sum(partials + (long)d * np, np);
+    if (threadIdx.x == 0) {
+        s.gam[d] = g;
+        s.active[d] = (g > 0.0 && isfinite(g)) ? 1 : 0;
+    }
+}
+
+__global__ void inner_alpha(InnerScalars s, const double* partials, int np, const int* done) {
+    if (done && *done) return;
+    const int d = blockIdx.x;
+    const double pw = domain_sum(partials + (long)d * np, np);
+    if (threadIdx.x == 0) {
+        int act = s.active[d] && pw > 0.0 && isfinite(pw);
+        s.active[d] = act;
+        s.a[d] = act ? s.gam[d] / pw : 0.0;
+    }
+}
+
+__global__ void inner_beta(InnerScalars s, const double* partials, int np, const int* done) {
+    if (done && *done) return;
+    const int d = blockIdx.x;
+    const double g2 = domain_sum(partials + (long)d * np, np);
+    if (threadIdx.x == 0) {
+        const int act = s.active[d];
+        s.beta[d] = act ? g2 / s.gam[d] : 0.0;
+        s.active[d] = act && g2 > 0.0 && isfinite(g2);
+        s.gam[d] = g2;
+    }
+}
+
+struct DomGeom {
+    int L[4], blk[4], nb[4];
+};
+
+// rho = p = r on the block interior (global FP64 layout -> domain layout),
+// per-domain |rho|^2 partials.
+template <class S>
+__global__ void inner_start_kernel(CField<F64> r, Field<S> rho, Field<S> p, DomGeom g, int Ls,
+                                   long Vhb, double* partials, const int* done) {
+    if (done && *done) return;
+    const int spb = blockDim.x / Ls;
+    const long cb = (long)blockIdx.x * spb + threadIdx.x / Ls;
+    const int s = threadIdx.x % Ls;
+    const int d = blockIdx.y;
+    const bool active = (int)threadIdx.x < spb * Ls && cb < Vhb;
+    double n2 = 0;
+    if (active) {
+        Box b;
+        for (int m = 0; m < 4; ++m) {
+            b.E[m] = g.blk[m];
+            b.off[m] = 0;
+        }
+        b.Vh = Vhb;
+        int c[4];
+        box_coords(b, cb, 0, c);
+        int rr = d, gc[4];
+        for (int m = 0; m < 4; ++m) {
+            gc[m] = (rr % g.nb[m]) * g.blk[m] + c[m];
+            rr /= g.nb[m];
+        }
+        const long gcb = ((((long)gc[3] * g.L[2] + gc[2]) * g.L[1] + gc[1]) * g.L[0] + gc[0]) >> 1;
+        cx<double> v[12];
+        load_spinor<F64>(r, gcb * Ls + s, v);
+        cx<typename S::real> w[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            w[k] = {(typename S::real)v[k].re, (typename S::real)v[k].im};
+            n2 += (double)w[k].re * w[k].re + (double)w[k].im * w[k].im;
+        }
+        const long i = ((long)d * Vhb + cb) * Ls + s;
+        store_spinor<S>(rho, i, w);
+        store_spinor<S>(p, i, w);
+    }
+    block_reduce_store(n2, partials + (long)d * gridDim.x + blockIdx.x);
+}
+
+// z += a p (z = a p on the first step) ; rho -= a w ; |rho|^2 partials
+template <class S>
+__global__ void inner_update_kernel(Field<S> z, Field<S> rho, CField<S> p, CField<S> w, long n_dom,
+                                    InnerScalars sc, int first, double* partials, const int* done) {
+    if (done && *done) return;
+    using T = typename S::real;
+    const int d = blockIdx.y;
+    const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double n2 = 0;
+    if (j < n_dom) {
+        const long i = (long)d * n_dom + j;
+        const T a = (T)sc.a[d];
+        cx<T> pv[12], wv[12], zv[12], rv[12];
+        load_spinor<S>(p, i, pv);
+        load_spinor<S>(w, i, wv);
+        load_spinor<S>(cfield(rho), i, rv);
+        if (!first) load_spinor<S>(cfield(z), i, zv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            if (first) zv[k] = {0, 0};
+            zv[k].re += a * pv[k].re;
+            zv[k].im += a * pv[k].im;
+            rv[k].re -= a * wv[k].re;
+            rv[k].im -= a * wv[k].im;
+            n2 += (double)rv[k].re * rv[k].re + (double)rv[k].im * rv[k].im;
+        }
+        store_spinor<S>(z, i, zv);
+        store_spinor<S>(rho, i, rv);
+    }
+    block_reduce_store(n2, partials + (long)d * gridDim.x + blockIdx.x);
+}
+
+// p = rho + beta p
+template <class S>
+__global__ void inner_xpay_kernel(Field<S> p, CField<S> rho, long n_dom, InnerScalars sc,
+                                  const int* done) {
+    if (done && *done) return;
+    using T = typename S::real;
+    const int d = blockIdx.y;
+    const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_dom) return;
+    const long i = (long)d * n_dom + j;
+    const T b = (T)sc.beta[d];
+    cx<T> pv[12], rv[12];
+    load_spinor<S>(cfield(p), i, pv);
+    load_spinor<S>(rho, i, rv);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        pv[k].re = rv[k].re + b * pv[k].re;
+        pv[k].im = rv[k].im + b * pv[k].im;
+    }
+    store_spinor<S>(p, i, pv);
+}
+
+int last_error() { return hipGetLastError() == hipSuccess ? 0 : MSPCG_EHIP; }
+
+}  // namespace
+
+static Box dom_box(const mspcg_ctx* c, const Domains& D, int padk) {
+    Box b;
+    long v = 1;
+    for (int m = 0; m < 4; ++m) {
+        if (D.nb[m] == 1) {
+            b.E[m] = c->L[m];
+            b.off[m] = 0;
+        } else {
+            b.E[m] = D.blk[m] + 2 * padk;
+            b.off[m] = -padk;
+        }
+        v *= b.E[m];
+    }
+    b.Vh = v / 2;
+    return b;
 }
 
 template <class S>
-int precond_apply(mspcg_ctx*, int, CField<F64>, Field<F64>, hipStream_t, int*) {
-    return MSPCG_EUNSUPPORTED;
+static size_t link_elems(const Domains& D) {
+    return (size_t)D.ndom * 2 * 8 * 9 * D.pad2.Vh;
+}
+
+int domains_setup(mspcg_ctx* c, const mspcg_blocking& bk, int prec, hipStream_t st) {
+    Domains& D = c->dom;
+    bool same = D.built && D.prec == prec && D.pad == bk.pad;
+    for (int m = 0; m < 4; ++m) same = same && D.blk[m] == bk.block[m];
+    if (same) return 0;
+    if (prec != MSPCG_FP16 && prec != MSPCG_FP32 && prec != MSPCG_FP64) return MSPCG_EINVAL;
+    if (bk.pad < 0 || bk.pad > 2) return MSPCG_EINVAL;
+    int ndom = 1;
+    for (int m = 0; m < 4; ++m) {
+        const int b = bk.block[m];
+        if (b < 2 || (b & 1) || c->L[m] % b) return MSPCG_EINVAL;
+        D.blk[m] = b;
+        D.nb[m] = c->L[m] / b;
+        // the padded domain must not reach around the lattice onto the block
+        if (D.nb[m] > 1 && c->L[m] - b < 2 * bk.pad) return MSPCG_EINVAL;
+        ndom *= D.nb[m];
+    }
+    if (ndom > kMaxDomains) return MSPCG_EUNSUPPORTED;
+    D.ndom = ndom;
+    D.pad = bk.pad;
+    D.interior = dom_box(c, D, 0);
+    D.pad1 = dom_box(c, D, bk.pad < 1 ? bk.pad : 1);
+    D.pad2 = dom_box(c, D, bk.pad < 2 ? bk.pad : 2);
+    D.Vh_int = D.interior.Vh;
+    if (D.links) (void)hipFree(D.links);
+    D.links = nullptr;
+    size_t esz = prec == MSPCG_FP64 ? sizeof(double2) : (prec == MSPCG_FP32 ? sizeof(float2) : sizeof(__half2));
+    const size_t n = (size_t)ndom * 2 * 8 * 9 * D.pad2.Vh;
+    if (hipMalloc(&D.links, n * esz) != hipSuccess) return MSPCG_ENOMEM;
+    int e = 0;
+    if (prec == MSPCG_FP64)
+        e = launch_pack_links<F64>(c->U, (double2*)D.links, c->L, D.blk, D.nb, D.pad2,
+                                   c->act.antiperiodic_t, st);
+    else if (prec == MSPCG_FP32)
+        e = launch_pack_links<F32>(c->U, (float2*)D.links, c->L, D.blk, D.nb, D.pad2,
+                                   c->act.antiperiodic_t, st);
+    else
+        e = launch_pack_links<F16>(c->U, (__half2*)D.links, c->L, D.blk, D.nb, D.pad2,
+                                   c->act.antiperiodic_t, st);
+    if (e) return MSPCG_EHIP;
+    D.prec = prec;
+    D.built = true;
+    return 0;
+}
+
+static int periodic_mask(const Domains& D) {
+    int m = 0;
+    for (int k = 0; k < 4; ++k)
+        if (D.nb[k] == 1) m |= 1 << k;
+    return m;
 }
 
 template <class S>
-int kblock_apply(mspcg_ctx*, CField<F64>, Field<F64>, hipStream_t) {
-    return MSPCG_EUNSUPPORTED;
+static int dom_hop(mspcg_ctx* c, Field<S> out, const Box& bout, CField<S> in, const Box& bin,
+                   int out_par, bool dag, const FiveDProg& ph, const CField<S>* aux,
+                   const Box& baux, const FiveDProg& pa, double* partials, const int* done,
+                   hipStream_t st) {
+    const Domains& D = c->dom;
+    HopArgs<S> a;
+    memset(&a, 0, sizeof(a));
+    a.in = in;
+    a.out = out;
+    if (aux) a.aux = *aux;
+    a.links = (const typename S::elem*)D.links;
+    a.link_dom_stride = 2L * 8 * 9 * D.pad2.Vh;
+    a.g.out = bout;
+    a.g.in = bin;
+    a.g.aux = aux ? baux : bout;
+    a.g.link = D.pad2;
+    a.g.out_par = out_par;
+    a.g.periodic = periodic_mask(D);
+    a.ph = ph;
+    a.pa = pa;
+    a.has_aux = aux != nullptr;
+    a.mf = c->act.mf;
+    a.partials = partials;
+    a.done = done;
+    const double bytes = (double)D.ndom * c->Ls *
+                             (double)(bout.Vh + bin.Vh + (aux ? baux.Vh : 0)) * S::bytes_spinor +
+                         (double)D.ndom * bout.Vh * 8 * S::bytes_link;
+    Timed t(c, MSPCG_KC_HOPDOM, bytes, st);
+    return launch_hop<S>(a, c->Ls, D.ndom, dag, st);
 }
 
-template int precond_apply<F64>(mspcg_ctx*, int, CField<F64>, Field<F64>, hipStream_t, int*);
-template int precond_apply<F32>(mspcg_ctx*, int, CField<F64>, Field<F64>, hipStream_t, int*);
-template int precond_apply<F16>(mspcg_ctx*, int, CField<F64>, Field<F64>, hipStream_t, int*);
-template int kblock_apply<F64>(mspcg_ctx*, CField<F64>, Field<F64>, hipStream_t);
-template int kblock_apply<F32>(mspcg_ctx*, CField<F64>, Field<F64>, hipStream_t);
-template int kblock_apply<F16>(mspcg_ctx*, CField<F64>, Field<F64>, hipStream_t);
+template <class S>
+static int dom_fived(mspcg_ctx* c, Field<S> out, CField<S> in, long Vh, const FiveDProg& p,
+                     const int* done, hipStream_t st) {
+    FiveDArgs<S> a;
+    a.in = in;
+    a.out = out;
+    a.Vh = Vh;
+    a.p = p;
+    a.mf = c->act.mf;
+    a.partials = nullptr;
+    a.done = done;
+    Timed t(c, MSPCG_KC_FIVED, (double)c->dom.ndom * Vh * c->Ls * S::bytes_spinor * 2, st);
+    return launch_fived<S>(a, c->Ls, c->dom.ndom, st);
+}
+
+// w = A_s p for every block: P_s Mhat_D^+ Mhat_D p (p supported on the block).
+// partials (optional) receive per-domain |Mhat_D p|^2 = <p, A_s p>, laid out
+// [ndom][hop_grid_x(pad2.Vh)].
+template <class S>
+static int block_A(mspcg_ctx* c, Field<S> w, CField<S> p, double* partials, const int* done,
+                   hipStream_t st) {
+    const Domains& D = c->dom;
+    const int Ls = c->Ls;
+    const std::string pf = std::string("dom") + (std::is_same<S, F16>::value ? "16." : std::is_same<S, F32>::value ? "32." : "64.");
+    Field<S> t = half_field<S>(c, pf + "t", (long)D.ndom * D.interior.Vh * Ls);
+    Field<S> u = half_field<S>(c, pf + "u", (long)D.ndom * D.pad1.Vh * Ls);
+    Field<S> y = half_field<S>(c, pf + "y", (long)D.ndom * D.pad2.Vh * Ls);
+    Field<S> v = half_field<S>(c, pf + "v", (long)D.ndom * D.pad1.Vh * Ls);
+    if (!t.data || !u.data || !y.data || !v.data) return MSPCG_ENOMEM;
+    const Progs& P = c->pr;
+    FiveDProg m14;
+    memset(&m14, 0, sizeof(m14));
+    m14.scale[0] = m14.scale[1] = -0.25;
+    m14.identity = 1;
+    int e;
+    // t = B p (block)
+    if ((e = dom_fived<S>(c, t, p, D.interior.Vh, P.B, done, st))) return e;
+    // u = X D_h^oe t  (odd, pad 1)
+    if ((e = dom_hop<S>(c, u, D.pad1, cfield(t), D.interior, 1, false, P.X, nullptr, D.interior,
+                        P.id, nullptr, done, st)))
+        return e;
+    // y = M5op p - D_h^eo u / 4  (even, pad 2) = Mhat_D p
+    if ((e = dom_hop<S>(c, y, D.pad2, cfield(u), D.pad1, 0, false, m14, &p, D.interior, P.M5,
+                        partials, done, st)))
+        return e;
+    // v = X^+ Dd^oe y  (odd, pad 1)
+    if ((e = dom_hop<S>(c, v, D.pad1, cfield(y), D.pad2, 1, true, P.Xdag, nullptr, D.interior,
+                        P.id, nullptr, done, st)))
+        return e;
+    // w = M5op^+ y - B^+ Dd^eo v / 4  (even, block)
+    CField<S> yc = cfield(y);
+    return dom_hop<S>(c, w, D.interior, cfield(v), D.pad1, 0, true, scaled(P.Bdag, -0.25, -0.25),
+                      &yc, D.pad2, P.M5dag, nullptr, done, st);
+}
+
+static InnerScalars inner_scalars(mspcg_ctx* c) {
+    InnerScalars s;
+    const int n = c->dom.ndom;
+    s.gam = (double*)c->buf("in.gam", n * sizeof(double));
+    s.a = (double*)c->buf("in.a", n * sizeof(double));
+    s.beta = (double*)c->buf("in.beta", n * sizeof(double));
+    s.active = (int*)c->buf("in.active", n * sizeof(int));
+    return s;
+}
+
+// z_e = K_l^-1 r_e (FP64 whole-lattice even fields); `done` (device flag,
+// may be null) skips the work once the outer solve has converged.
+template <class S>
+static int precond_core(mspcg_ctx* c, int l, CField<F64> r, Field<F64> z, const int* done,
+                        hipStream_t st) {
+    const Domains& D = c->dom;
+    const int Ls = c->Ls;
+    const long nd = D.interior.Vh * Ls;  // (site, s) per domain
+    const std::string pf = std::string("dom") + (std::is_same<S, F16>::value ? "16." : std::is_same<S, F32>::value ? "32." : "64.");
+    Field<S> rho = half_field<S>(c, pf + "rho", D.ndom * nd);
+    Field<S> p = half_field<S>(c, pf + "p", D.ndom * nd);
+    Field<S> zz = half_field<S>(c, pf + "z", D.ndom * nd);
+    Field<S> w = half_field<S>(c, pf + "w", D.ndom * nd);
+    if (!rho.data || !p.data || !zz.data || !w.data) return MSPCG_ENOMEM;
+    InnerScalars sc = inner_scalars(c);
+    const long hop_np = hop_grid_x<S>(D.pad2.Vh, Ls);
+    const int spb = kThreads / Ls;
+    const long start_np = (D.interior.Vh + spb - 1) / spb;
+    const long vec_np = (nd + kThreads - 1) / kThreads;
+    long need = hop_np > start_np ? hop_np : start_np;
+    if (vec_np > need) need = vec_np;
+    int e = ensure_partials(c, (size_t)(D.ndom * need + 64));
+    if (e) return e;
+    double* part = c->partials;
+    DomGeom g;
+    for (int m = 0; m < 4; ++m) {
+        g.L[m] = c->L[m];
+        g.blk[m] = D.blk[m];
+        g.nb[m] = D.nb[m];
+    }
+    {
+        Timed t(c, MSPCG_KC_BLAS, (double)D.ndom * nd * (192.0 + 2 * S::bytes_spinor), st);
+        hipLaunchKernelGGL(inner_start_kernel<S>, dim3((unsigned)start_np, D.ndom), dim3(spb * Ls),
+                           0, st, r, rho, p, g, Ls, D.interior.Vh, part, done);
+        if (last_error()) return MSPCG_EHIP;
+        hipLaunchKernelGGL(inner_start_scalars, dim3(D.ndom), dim3(kThreads), 0, st, sc, part,
+                           (int)start_np, done);
+        if (last_error()) return MSPCG_EHIP;
+    }
+    for (int it = 0; it < l; ++it) {
+        if ((e = block_A<S>(c, w, cfield(p), part, done, st))) return e;
+        Timed t(c, MSPCG_KC_BLAS, (double)D.ndom * nd * S::bytes_spinor * (it ? 9 : 8), st);
+        hipLaunchKernelGGL(inner_alpha, dim3(D.ndom), dim3(kThreads), 0, st, sc, part, (int)hop_np,
+                           done);
+        hipLaunchKernelGGL(inner_update_kernel<S>, dim3((unsigned)vec_np, D.ndom), dim3(kThreads),
+                           0, st, zz, rho, cfield(p), cfield(w), nd, sc, it == 0 ? 1 : 0, part,
+                           done);
+        if (it + 1 < l) {
+            hipLaunchKernelGGL(inner_beta, dim3(D.ndom), dim3(kThreads), 0, st, sc, part,
+                               (int)vec_np, done);
+            hipLaunchKernelGGL(inner_xpay_kernel<S>, dim3((unsigned)vec_np, D.ndom), dim3(kThreads),
+                               0, st, p, cfield(rho), nd, sc, done);
+        }
+        if (last_error()) return MSPCG_EHIP;
+    }
+    Timed t(c, MSPCG_KC_BLAS, (double)D.ndom * nd * (192.0 + S::bytes_spinor), st);
+    if (l == 0) {
+        MSPCG_HIP(hipMemsetAsync(z.data, 0, (size_t)12 * c->Nh * sizeof(double2), st));
+        return 0;
+    }
+    if (launch_domain_to_global<S, F64>(cfield(zz), z, c->L, D.blk, D.nb, Ls, 0, st))
+        return MSPCG_EHIP;
+    return 0;
+}
+
+size_t precond_partials_need(mspcg_ctx* c) {
+    const Domains& D = c->dom;
+    const int Ls = c->Ls;
+    const long nd = D.interior.Vh * Ls;
+    const long hop_np = hop_grid_x<F64>(D.pad2.Vh, Ls);
+    const int spb = kThreads / Ls;
+    const long start_np = (D.interior.Vh + spb - 1) / spb;
+    const long vec_np = (nd + kThreads - 1) / kThreads;
+    long need = hop_np > start_np ? hop_np : start_np;
+    if (vec_np > need) need = vec_np;
+    return (size_t)(D.ndom * need + 64);
+}
+
+template <class S>
+int precond_apply(mspcg_ctx* c, int l, CField<F64> r, Field<F64> z, hipStream_t st, int*) {
+    return precond_core<S>(c, l, r, z, nullptr, st);
+}
+
+template <class S>
+int precond_apply_flag(mspcg_ctx* c, int l, CField<F64> r, Field<F64> z, const int* done,
+                       hipStream_t st) {
+    return precond_core<S>(c, l, r, z, done, st);
+}
+
+template <class S>
+int kblock_apply(mspcg_ctx* c, CField<F64> p_e, Field<F64> q_e, hipStream_t st) {
+    const Domains& D = c->dom;
+    const int Ls = c->Ls;
+    const long nd = D.interior.Vh * Ls;
+    const std::string pf = std::string("dom") + (std::is_same<S, F16>::value ? "16." : std::is_same<S, F32>::value ? "32." : "64.");
+    Field<S> p = half_field<S>(c, pf + "p", D.ndom * nd);
+    Field<S> w = half_field<S>(c, pf + "w", D.ndom * nd);
+    if (!p.data || !w.data) return MSPCG_ENOMEM;
+    if (launch_global_to_domain<F64, S>(p_e, p, c->L, D.blk, D.nb, Ls, 0, st)) return MSPCG_EHIP;
+    int e = block_A<S>(c, w, cfield(p), nullptr, nullptr, st);
+    if (e) return e;
+    if (launch_domain_to_global<S, F64>(cfield(w), q_e, c->L, D.blk, D.nb, Ls, 0, st))
+        return MSPCG_EHIP;
+    return 0;
+}
+
+#define MSPCG_PC(S)                                                                         \
+    template int precond_apply<S>(mspcg_ctx*, int, CField<F64>, Field<F64>, hipStream_t,   \
+                                  int*);                                                    \
+    template int precond_apply_flag<S>(mspcg_ctx*, int, CField<F64>, Field<F64>,           \
+                                       const int*, hipStream_t);                            \
+    template int kblock_apply<S>(mspcg_ctx*, CField<F64>, Field<F64>, hipStream_t);
+MSPCG_PC(F64)
+MSPCG_PC(F32)
+MSPCG_PC(F16)
 
 }  // namespace mspcg

@@ -141,11 +141,14 @@ int cg_fp64(mspcg_ctx* c, CField<F64> bhat, Field<F64> x, bool x0, const mspcg_s
                 converged = true;
                 break;
             }
-            // reliable update: continue from the true residual
+            // continue from the true residual: the step that set `done` skipped
+            // p = r + beta p, so redo it with beta = |r_true|^2 / |r_prev|^2
             restarts++;
+            s.beta = s.beta * true_rr / s.rr;
             s.rr = true_rr;
             s.done = 0;
             if ((e = push(c, st, s))) return e;
+            if (launch_xpay(pp.data, r.data, c->Nh, c->sc, 0, st)) return MSPCG_EHIP;
         }
         if (iters >= p->maxiter) {
             if ((e = true_residual(c, r, bhat, cfield(x), st, true_rr))) return e;
@@ -171,12 +174,228 @@ int cg_fp64(mspcg_ctx* c, CField<F64> bhat, Field<F64> x, bool x0, const mspcg_s
     return converged ? MSPCG_OK : MSPCG_ENOCONV;
 }
 
+void fill_stats(mspcg_ctx* c, mspcg_solve_stats* stats, int iters, int inner, int restarts,
+                bool converged, double true_rr, double bb, const double* hist_dev) {
+    if (!stats) return;
+    stats->outer_iters = iters;
+    stats->inner_iters_total = inner;
+    stats->restarts = restarts;
+    stats->converged = converged ? 1 : 0;
+    stats->true_rel_resid = sqrt(true_rr / bb);
+    stats->resid_history_len = 0;
+    if (stats->resid_history && stats->resid_history_cap > 0 && hist_dev) {
+        const int n = iters < stats->resid_history_cap ? iters : stats->resid_history_cap;
+        if (n > 0) {
+            std::vector<double> h(n);
+            if (hipMemcpy(h.data(), hist_dev, n * sizeof(double), hipMemcpyDeviceToHost) ==
+                hipSuccess) {
+                for (int i = 0; i < n; ++i) stats->resid_history[i] = sqrt(h[i] / bb);
+                stats->resid_history_len = n;
+            }
+        }
+    }
+}
+
+// Flexible preconditioned CG (FP64) with z = K_l^-1 r in storage precision S.
+template <class S>
+int mspcg_fp64(mspcg_ctx* c, CField<F64> bhat, Field<F64> x, bool x0,
+               const mspcg_solve_params* p, double bb, mspcg_solve_stats* stats, hipStream_t st) {
+    Field<F64> r = half_field<F64>(c, "d.cg_r", c->Nh);
+    Field<F64> pp = half_field<F64>(c, "d.cg_p", c->Nh);
+    Field<F64> q = half_field<F64>(c, "d.cg_q", c->Nh);
+    Field<F64> z = half_field<F64>(c, "d.cg_z", c->Nh);
+    if (!r.data || !pp.data || !q.data || !z.data) return MSPCG_ENOMEM;
+    int e;
+    if ((e = domains_setup(c, p->blocking, p->inner_prec, st))) return e;
+    const long nph = hop_nparts(c);
+    const long npb = blas_grid_x(12 * c->Nh);
+    size_t need = 4 * (size_t)(nph > npb ? nph : npb) + 16;
+    const size_t pneed = precond_partials_need(c);
+    if (pneed > need) need = pneed;
+    if ((e = ensure_partials(c, need))) return e;
+    const int cap = p->maxiter + 1;
+    if ((e = ensure_hist(c, cap))) return e;
+    const int l = p->inner_iters;
+    double rr;
+    if (x0) {
+        if ((e = true_residual(c, r, bhat, cfield(x), st, rr))) return e;
+    } else {
+        MSPCG_HIP(hipMemsetAsync(x.data, 0, (size_t)12 * c->Nh * sizeof(double2), st));
+        if ((e = norm2_sync(c, bhat.data, r.data, st, rr))) return e;
+    }
+    DevScalars s;
+    memset(&s, 0, sizeof(s));
+    s.rr = rr;
+    s.bb = bb;
+    s.tol2 = p->tol * p->tol * bb;
+    s.done = rr <= s.tol2 ? 1 : 0;
+    if ((e = push(c, st, s))) return e;
+    // (re)start: z = K r ; p = z ; zr = <z, r>   (alpha = 0 makes beta = 0)
+    auto restart = [&]() -> int {
+        int e2;
+        if ((e2 = precond_apply_flag<S>(c, l, cfield(r), z, &c->sc->done, st))) return e2;
+        MSPCG_HIP(hipMemsetAsync(pp.data, 0, (size_t)12 * c->Nh * sizeof(double2), st));
+        if (launch_dot2(z.data, r.data, r.data, c->Nh, c->partials, npb, st)) return MSPCG_EHIP;
+        if (launch_fpcg_beta(c->sc, c->partials, (int)npb, st)) return MSPCG_EHIP;
+        if (launch_xpay(pp.data, z.data, c->Nh, c->sc, 0, st)) return MSPCG_EHIP;
+        return 0;
+    };
+    if (!s.done && (e = restart())) return e;
+    const int check = p->check_every > 0 ? p->check_every : 4;
+    int restarts = 0, iters = 0;
+    bool converged = false;
+    double true_rr = rr;
+    while (true) {
+        if (!s.done) {
+            for (int k = 0; k < check && iters + k < p->maxiter; ++k) {
+                if ((e = op_A<F64>(c, q, cfield(pp), c->partials, &c->sc->done, st))) return e;
+                if (launch_cg_alpha(c->sc, c->partials, (int)nph, st, 1)) return MSPCG_EHIP;
+                if (launch_cg_update_xr(x.data, r.data, pp.data, q.data, c->Nh, c->sc, c->partials,
+                                        npb, st))
+                    return MSPCG_EHIP;
+                if (launch_cg_beta(c->sc, c->partials, (int)npb, c->hist, cap, st)) return MSPCG_EHIP;
+                if ((e = precond_apply_flag<S>(c, l, cfield(r), z, &c->sc->done, st))) return e;
+                if (launch_dot2(z.data, r.data, q.data, c->Nh, c->partials, npb, st)) return MSPCG_EHIP;
+                if (launch_fpcg_beta(c->sc, c->partials, (int)npb, st)) return MSPCG_EHIP;
+                if (launch_xpay(pp.data, z.data, c->Nh, c->sc, 0, st)) return MSPCG_EHIP;
+            }
+            if ((e = poll(c, st, s))) return e;
+        }
+        iters = s.iter;
+        if (s.breakdown) {
+            fill_stats(c, stats, iters, iters * l, restarts, false, s.rr, bb, c->hist);
+            return MSPCG_EBREAKDOWN;
+        }
+        if (s.done) {
+            if ((e = true_residual(c, r, bhat, cfield(x), st, true_rr))) return e;
+            if (true_rr <= s.tol2) {
+                converged = true;
+                break;
+            }
+            restarts++;
+            s.rr = true_rr;
+            s.done = 0;
+            s.alpha = 0.0;
+            if ((e = push(c, st, s))) return e;
+            if ((e = restart())) return e;
+            if ((e = poll(c, st, s))) return e;
+        }
+        if (iters >= p->maxiter) {
+            if ((e = true_residual(c, r, bhat, cfield(x), st, true_rr))) return e;
+            break;
+        }
+    }
+    fill_stats(c, stats, iters, (iters + 1 + restarts) * l, restarts, converged, true_rr, bb,
+               c->hist);
+    return converged ? MSPCG_OK : MSPCG_ENOCONV;
+}
+
+// Mixed-precision CG: FP32 iterations on A, FP64 solution, and a reliable
+// update (FP64 true residual, FP32 iterate folded into x) whenever the
+// iterated residual has dropped by delta since the last update.
+int mixed_cg(mspcg_ctx* c, CField<F64> bhat, Field<F64> x, bool x0, const mspcg_solve_params* p,
+             double bb, mspcg_solve_stats* stats, hipStream_t st) {
+    Field<F64> r = half_field<F64>(c, "d.cg_r", c->Nh);
+    Field<F32> rs = half_field<F32>(c, "s.cg_r", c->Nh);
+    Field<F32> ps = half_field<F32>(c, "s.cg_p", c->Nh);
+    Field<F32> qs = half_field<F32>(c, "s.cg_q", c->Nh);
+    Field<F32> xs = half_field<F32>(c, "s.cg_x", c->Nh);
+    if (!r.data || !rs.data || !ps.data || !qs.data || !xs.data) return MSPCG_ENOMEM;
+    const long nph = hop_nparts(c);
+    const long npb = blas_grid_x(12 * c->Nh);
+    int e;
+    if ((e = ensure_partials(c, 4 * (size_t)(nph > npb ? nph : npb) + 16))) return e;
+    const int cap = p->maxiter + 1;
+    if ((e = ensure_hist(c, cap))) return e;
+    const double delta = p->delta > 0 ? p->delta : 0.1;
+    double rr;
+    if (x0) {
+        if ((e = true_residual(c, r, bhat, cfield(x), st, rr))) return e;
+    } else {
+        MSPCG_HIP(hipMemsetAsync(x.data, 0, (size_t)12 * c->Nh * sizeof(double2), st));
+        if ((e = norm2_sync(c, bhat.data, r.data, st, rr))) return e;
+    }
+    MSPCG_HIP(hipMemsetAsync(xs.data, 0, (size_t)12 * c->Nh * sizeof(float2), st));
+    if (launch_convert<F64, F32>(cfield(r), rs, c->Nh, st)) return MSPCG_EHIP;
+    MSPCG_HIP(hipMemcpyAsync(ps.data, rs.data, (size_t)12 * c->Nh * sizeof(float2),
+                             hipMemcpyDeviceToDevice, st));
+    DevScalars s;
+    memset(&s, 0, sizeof(s));
+    s.rr = rr;
+    s.bb = bb;
+    s.tol2 = p->tol * p->tol * bb;
+    double rr_update = rr;  // |r|^2 at the last reliable update
+    // the FP32 loop stops (done) at tol2 or when |r|^2 fell by delta^2
+    auto set_target = [&](DevScalars& d) {
+        const double t = delta * delta * rr_update;
+        d.tol2 = t > p->tol * p->tol * bb ? t : p->tol * p->tol * bb;
+    };
+    set_target(s);
+    s.done = rr <= p->tol * p->tol * bb ? 1 : 0;
+    if ((e = push(c, st, s))) return e;
+    const int check = p->check_every > 0 ? p->check_every : 8;
+    int updates = 0, iters = 0;
+    bool converged = false;
+    double true_rr = rr;
+    const double tol2 = p->tol * p->tol * bb;
+    while (true) {
+        if (!s.done) {
+            for (int k = 0; k < check && iters + k < p->maxiter; ++k) {
+                if ((e = op_A<F32>(c, qs, cfield(ps), c->partials, &c->sc->done, st))) return e;
+                if (launch_cg_alpha(c->sc, c->partials, (int)nph, st, 0)) return MSPCG_EHIP;
+                if (launch_cg_update_xr32(xs.data, rs.data, ps.data, qs.data, c->Nh, c->sc,
+                                          c->partials, npb, st))
+                    return MSPCG_EHIP;
+                if (launch_cg_beta(c->sc, c->partials, (int)npb, c->hist, cap, st)) return MSPCG_EHIP;
+                if (launch_xpay32(ps.data, rs.data, c->Nh, c->sc, st)) return MSPCG_EHIP;
+            }
+            if ((e = poll(c, st, s))) return e;
+        }
+        iters = s.iter;
+        if (s.breakdown) {
+            fill_stats(c, stats, iters, 0, updates, false, s.rr, bb, c->hist);
+            return MSPCG_EBREAKDOWN;
+        }
+        if (s.done || iters >= p->maxiter) {
+            // reliable update: x += xs ; r = bhat - A x in FP64 ; rs = r
+            if (launch_accum32(x.data, xs.data, c->Nh, st)) return MSPCG_EHIP;
+            if ((e = true_residual(c, r, bhat, cfield(x), st, true_rr))) return e;
+            updates++;
+            if (true_rr <= tol2) {
+                converged = true;
+                break;
+            }
+            if (iters >= p->maxiter) break;
+            if (launch_convert<F64, F32>(cfield(r), rs, c->Nh, st)) return MSPCG_EHIP;
+            rr_update = true_rr;
+            // keep the search direction: p = r + beta p with beta = |r_true|^2 / |r_prev|^2
+            s.beta = s.rr > 0 ? s.beta * true_rr / s.rr : 0.0;
+            s.rr = true_rr;
+            s.done = 0;
+            set_target(s);
+            if ((e = push(c, st, s))) return e;
+            if (launch_xpay32(ps.data, rs.data, c->Nh, c->sc, st)) return MSPCG_EHIP;
+        }
+    }
+    fill_stats(c, stats, iters, 0, updates, converged, true_rr, bb, c->hist);
+    return converged ? MSPCG_OK : MSPCG_ENOCONV;
+}
+
 }  // namespace
 
 int solve_one(mspcg_ctx* c, const void* b_dev, void* x_dev, const mspcg_solve_params* p,
               mspcg_solve_stats* stats, hipStream_t st) {
     if (p->maxiter < 0 || !(p->tol > 0)) return MSPCG_EINVAL;
-    if (p->solver != MSPCG_SOLVER_CG) return MSPCG_EUNSUPPORTED;
+    if (p->solver < MSPCG_SOLVER_CG || p->solver > MSPCG_SOLVER_MSPCG) return MSPCG_EINVAL;
+    if (p->solver == MSPCG_SOLVER_MSPCG) {
+        if (p->inner_iters < 0) return MSPCG_EINVAL;
+        if (p->inner_prec < MSPCG_FP64 || p->inner_prec > MSPCG_FP16) return MSPCG_EINVAL;
+        for (int m = 0; m < 4; ++m) {
+            const int b = p->blocking.block[m];
+            if (b < 2 || (b & 1) || c->L[m] % b) return MSPCG_EINVAL;
+        }
+        if (p->blocking.pad < 0 || p->blocking.pad > 2) return MSPCG_EINVAL;
+    }
     c->timing = p->timing != 0;
     timing_reset(c);
     const Progs& P = c->pr;
@@ -220,7 +439,16 @@ int solve_one(mspcg_ctx* c, const void* b_dev, void* x_dev, const mspcg_solve_pa
         }
         rc = MSPCG_OK;
     } else {
-        rc = cg_fp64(c, cfield(bhat), xe, p->use_x0 != 0, p, bb, stats, st);
+        if (p->solver == MSPCG_SOLVER_CG)
+            rc = cg_fp64(c, cfield(bhat), xe, p->use_x0 != 0, p, bb, stats, st);
+        else if (p->solver == MSPCG_SOLVER_MIXED_CG)
+            rc = mixed_cg(c, cfield(bhat), xe, p->use_x0 != 0, p, bb, stats, st);
+        else if (p->inner_prec == MSPCG_FP16)
+            rc = mspcg_fp64<F16>(c, cfield(bhat), xe, p->use_x0 != 0, p, bb, stats, st);
+        else if (p->inner_prec == MSPCG_FP32)
+            rc = mspcg_fp64<F32>(c, cfield(bhat), xe, p->use_x0 != 0, p, bb, stats, st);
+        else
+            rc = mspcg_fp64<F64>(c, cfield(bhat), xe, p->use_x0 != 0, p, bb, stats, st);
         if (rc != MSPCG_OK && rc != MSPCG_ENOCONV) return rc;
     }
     // x_o = M5op^-1 (b_o + (1/2) D_h^oe B x_e)
