@@ -129,7 +129,20 @@ typedef struct {
     int check_every;      /* host convergence poll interval in iterations (0: auto) */
     double delta;         /* reliable-update threshold of the mixed CG (0: 0.1) */
     int timing;           /* 1: record per-kernel-class times with HIP events */
+    int rhs_normal;       /* 1: b is an even field solved directly as A x = b (x: even
+                             field, odd sites zero); 0: solve D x = b */
 } mspcg_solve_params;
+
+/* Launch tuning.  Hop kernels visit their output sites in 4D tiles so that
+ * concurrently running workgroups share neighbour spinors in L2; tile[p] is
+ * the preferred tile for precision p (MSPCG_FP64/FP32/FP16; all zero =
+ * lexicographic order; each extent is reduced to the largest even divisor of
+ * the box extent).  xcd_remap = 1 gives each of the 8 XCDs one contiguous
+ * range of tiles. */
+typedef struct {
+    int xcd_remap;
+    int tile[3][4];
+} mspcg_tuning;
 
 /* Kernel classes reported by the timing facility. */
 enum {
@@ -196,10 +209,26 @@ int mspcg_solve_batch(mspcg_ctx* const* ctxs, int n, const void* const* b_dev, v
                       const mspcg_solve_params* params, mspcg_solve_stats* stats,
                       hipStream_t stream);
 
-/* HMC fermion force of S = phi^+ A^-1 phi.  X = A^-1 phi and Y = Mhat X are
- * even fields; F (gauge layout) receives, per link, the traceless Hermitian
- * matrix with dS/deps = tr(T F_mu(x)) for U_mu(x) -> exp(i eps T) U_mu(x). */
-int mspcg_force(mspcg_ctx* ctx, const void* X_dev, const void* Y_dev, void* F_dev,
+/* Read / replace the context's launch tuning (see mspcg_tuning). */
+int mspcg_get_tuning(mspcg_ctx* ctx, mspcg_tuning* tuning);
+int mspcg_set_tuning(mspcg_ctx* ctx, const mspcg_tuning* tuning);
+
+/* Autotuner: times candidate traversal tiles and the XCD remap on this
+ * context's lattice (A in FP64 and FP32; the block operator in FP16 when
+ * blocking is not NULL) with HIP events and keeps the fastest.  Results are
+ * cached per (dims, Ls, blocking) in the text file cache_path when it is not
+ * NULL (read first, appended after tuning).  Needs the gauge field. */
+int mspcg_autotune(mspcg_ctx* ctx, const mspcg_blocking* blocking, const char* cache_path,
+                   hipStream_t stream);
+
+/* HMC fermion force of S = phi^+ A^-1 phi (the solve inside ensemble
+ * generation, Sec. 1.1).  X = A^-1 phi and Y = Mhat X are even fields.
+ * F (gauge layout, may be NULL) receives per link the traceless Hermitian
+ * matrix with dS/deps = tr(T F_mu(x)) for U_mu(x) -> exp(i eps T) U_mu(x);
+ * G (gauge layout, may be NULL) receives the gradient with respect to the
+ * unconstrained complex link, dS = Re sum_ij conj(G_ij) dU_ij.  At least one
+ * of F and G must be given.  Returns after the stream has completed. */
+int mspcg_force(mspcg_ctx* ctx, const void* X_dev, const void* Y_dev, void* F_dev, void* G_dev,
                 hipStream_t stream);
 
 #ifdef __cplusplus

@@ -168,10 +168,10 @@ def hop_sites(act: Action, U, psi, sites, dagger=False, block=None) -> np.ndarra
     U = _f(U, act.gshape)
     psi = _f(psi, act.fshape)
     sites = np.ascontiguousarray(sites, dtype=np.int64)
-    out = np.zeros(act.fshape, dtype=np.complex128)
+    out = np.empty((act.Ls, len(sites), 4, 3), dtype=np.complex128)
     _load().orc_hop_sites(_ivec(act.dims), act.Ls, int(act.antiperiodic_t), _ivec(block), _p(U),
                           _p(psi), _p(out), int(dagger), _p(sites), len(sites))
-    return out.reshape(act.Ls, act.V4, 4, 3)[:, sites]
+    return out
 
 
 def ktilde(act: Action, psi, dagger=False) -> np.ndarray:

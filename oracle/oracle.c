@@ -128,8 +128,8 @@ static inline void coords_of(const int L[4], long lex, int c[4]) {
  * blk != NULL: block-Dirichlet restriction, a term is dropped iff its source
  * site lies in a different block (blocks of extent blk[mu], origins at
  * multiples of blk[mu]) than the output site.
- * only_sites != NULL: compute only those nsites output sites (all s); the
- * other output entries are left untouched. */
+ * only_sites != NULL: compute only those nsites output sites (all s) and
+ * write them compactly as out[s][it][spin][colour]. */
 static void hop_impl(const int L[4], int Ls, int antiperiodic_t, const int *blk,
                      const cplx *U, const cplx *in, cplx *out, int dagger,
                      const long *only_sites, long nsites) {
@@ -188,7 +188,9 @@ static void hop_impl(const int L[4], int Ls, int antiperiodic_t, const int *blk,
                         }
                 }
             }
-            memcpy(out + ((long)s * V4 + x) * 12, acc, sizeof(acc));
+            /* full mode: out[s][site]; site-list mode: compact out[s][it] */
+            const long o = only_sites ? ((long)s * nsites + it) : ((long)s * V4 + x);
+            memcpy(out + o * 12, acc, sizeof(acc));
         }
     }
 }

@@ -142,6 +142,27 @@ F16::elem* links_of<F16>(mspcg_ctx* c) { return c->L16; }
 
 long hop_nparts(mspcg_ctx* c) { return hop_grid_x<F64>(c->Vh, c->Ls); }
 
+void pick_tile(const int pref[4], const Box& b, int out[4]) {
+    bool any = false;
+    for (int m = 0; m < 4; ++m) any = any || pref[m] > 0;
+    for (int m = 0; m < 4; ++m) {
+        out[m] = 0;
+        if (!any) continue;
+        int t = pref[m] > 0 ? pref[m] : b.E[m];
+        if (t > b.E[m]) t = b.E[m];
+        t &= ~1;
+        while (t > 2 && b.E[m] % t) t -= 2;
+        out[m] = t < 2 ? 2 : t;
+    }
+}
+
+template <>
+int prec_index<F64>() { return MSPCG_FP64; }
+template <>
+int prec_index<F32>() { return MSPCG_FP32; }
+template <>
+int prec_index<F16>() { return MSPCG_FP16; }
+
 template <class S>
 static int kc_hop() {
     return std::is_same<S, F64>::value ? MSPCG_KC_HOP64
@@ -169,6 +190,8 @@ int op_hop(mspcg_ctx* c, Field<S> out, CField<S> in, int out_par, bool dag, cons
     a.mf = c->act.mf;
     a.partials = partials;
     a.done = done;
+    a.xcd_remap = c->tune.xcd_remap;
+    pick_tile(c->tune.tile[prec_index<S>()], c->lat, a.tile);
     const double bytes = (double)c->Nh * S::bytes_spinor * (2 + (aux ? 1 : 0)) +
                          (double)c->Vh * 8 * S::bytes_link;
     Timed t(c, kc_hop<S>(), bytes, st);
@@ -328,6 +351,15 @@ extern "C" int mspcg_create(const mspcg_action* a, int device, mspcg_ctx** out) 
     memset(&c->dom, 0, sizeof(c->dom));
     c->timing = false;
     c->evused = 0;
+    // measured defaults: 4D tiles help the FP64/FP32 whole-lattice hop, the
+    // lexicographic order is best for the FP16 block hops
+    c->tune.xcd_remap = 1;
+    const int t64[4] = {8, 4, 4, 4};
+    for (int m = 0; m < 4; ++m) {
+        c->tune.tile[MSPCG_FP64][m] = t64[m];
+        c->tune.tile[MSPCG_FP32][m] = t64[m];
+        c->tune.tile[MSPCG_FP16][m] = 0;
+    }
     c->hist_cap = 0;
     c->hist = nullptr;
     if (hipMalloc(&c->sc, sizeof(DevScalars)) != hipSuccess ||
@@ -488,6 +520,22 @@ extern "C" int mspcg_apply(mspcg_ctx* c, int op, int prec, const void* in_dev, v
     return MSPCG_EINVAL;
 }
 
+extern "C" int mspcg_get_tuning(mspcg_ctx* c, mspcg_tuning* t) {
+    if (!c || !t) return MSPCG_EINVAL;
+    *t = c->tune;
+    return MSPCG_OK;
+}
+
+extern "C" int mspcg_set_tuning(mspcg_ctx* c, const mspcg_tuning* t) {
+    if (!c || !t) return MSPCG_EINVAL;
+    for (int p = 0; p < 3; ++p)
+        for (int m = 0; m < 4; ++m)
+            if (t->tile[p][m] < 0 || (t->tile[p][m] & 1)) return MSPCG_EINVAL;
+    c->tune = *t;
+    c->tune.xcd_remap = t->xcd_remap ? 1 : 0;
+    return MSPCG_OK;
+}
+
 extern "C" int mspcg_set_blocking(mspcg_ctx* c, const mspcg_blocking* b) {
     if (!c || !b) return MSPCG_EINVAL;
     for (int m = 0; m < 4; ++m) {
@@ -537,13 +585,6 @@ extern "C" int mspcg_solve_batch(mspcg_ctx* const* ctxs, int n, const void* cons
                                  mspcg_solve_stats* stats, hipStream_t st) {
     if (!ctxs || n < 0 || !b_dev || !x_dev || !p) return MSPCG_EINVAL;
     (void)stats;
-    (void)st;
-    return MSPCG_EUNSUPPORTED;
-}
-
-extern "C" int mspcg_force(mspcg_ctx* c, const void* X_dev, const void* Y_dev, void* F_dev,
-                           hipStream_t st) {
-    if (!c || !X_dev || !Y_dev || !F_dev) return MSPCG_EINVAL;
     (void)st;
     return MSPCG_EUNSUPPORTED;
 }

@@ -103,34 +103,83 @@ __device__ __forceinline__ void load_spinor(CField<S> f, long i, cx<typename S::
     }
 }
 
+// Single-use streams (hop outputs, links) bypass L2 allocation with
+// nontemporal accesses so that the L2 keeps the neighbour spinors, which are
+// re-read by up to eight output sites.
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+
 template <class S>
+__device__ __forceinline__ void store_elem_nt(typename S::elem* p, typename S::real re,
+                                              typename S::real im) {
+    if constexpr (S::has_scale) {
+        const __half2 h = __floats2half2_rn(re, im);
+        __builtin_nontemporal_store(*reinterpret_cast<const unsigned*>(&h),
+                                    reinterpret_cast<unsigned*>(p));
+    } else if constexpr (sizeof(typename S::real) == 8) {
+        nt_d2 t = {re, im};
+        __builtin_nontemporal_store(t, reinterpret_cast<nt_d2*>(p));
+    } else {
+        nt_f2 t = {re, im};
+        __builtin_nontemporal_store(t, reinterpret_cast<nt_f2*>(p));
+    }
+}
+
+template <class S, bool NT = false>
 __device__ __forceinline__ void store_spinor(Field<S> f, long i, const cx<typename S::real> (&v)[12]) {
     if constexpr (S::has_scale) {
         float m = 0.f;
 #pragma unroll
         for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
         const float inv = m > 0.f ? 1.0f / m : 0.f;
-        f.scale[i] = m;
+        if (NT)
+            __builtin_nontemporal_store(m, f.scale + i);
+        else
+            f.scale[i] = m;
 #pragma unroll
-        for (int c = 0; c < 12; ++c)
-            f.data[c * f.N + i] = __floats2half2_rn(v[c].re * inv, v[c].im * inv);
+        for (int c = 0; c < 12; ++c) {
+            if (NT)
+                store_elem_nt<S>(f.data + c * f.N + i, v[c].re * inv, v[c].im * inv);
+            else
+                f.data[c * f.N + i] = __floats2half2_rn(v[c].re * inv, v[c].im * inv);
+        }
     } else {
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            typename S::elem t;
-            t.x = v[c].re;
-            t.y = v[c].im;
-            f.data[c * f.N + i] = t;
+            if (NT) {
+                store_elem_nt<S>(f.data + c * f.N + i, v[c].re, v[c].im);
+            } else {
+                typename S::elem t;
+                t.x = v[c].re;
+                t.y = v[c].im;
+                f.data[c * f.N + i] = t;
+            }
         }
     }
 }
 
-template <class S>
+template <class S, bool NT = false>
 __device__ __forceinline__ cx<typename S::real> load_link(const typename S::elem* p) {
     if constexpr (S::has_scale) {
+        if (NT) {
+            const unsigned u = __builtin_nontemporal_load(reinterpret_cast<const unsigned*>(p));
+            const float2 t = __half22float2(*reinterpret_cast<const __half2*>(&u));
+            return {t.x, t.y};
+        }
         const float2 t = __half22float2(*p);
         return {t.x, t.y};
+    } else if constexpr (sizeof(typename S::real) == 8) {
+        if (NT) {
+            const nt_d2 t = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+            return {t.x, t.y};
+        }
+        const auto t = *p;
+        return {t.x, t.y};
     } else {
+        if (NT) {
+            const nt_f2 t = __builtin_nontemporal_load(reinterpret_cast<const nt_f2*>(p));
+            return {t.x, t.y};
+        }
         const auto t = *p;
         return {t.x, t.y};
     }

@@ -81,6 +81,8 @@ struct mspcg_ctx {
     mspcg_blocking blocking;
     bool has_blocking;
     mspcg::Domains dom;
+    // launch tuning (traversal tiles per precision, XCD remap)
+    mspcg_tuning tune;
     // timing
     bool timing;
     std::vector<mspcg::TimingRec> trecs;
@@ -130,6 +132,11 @@ template <class S>
 int op_A(mspcg_ctx* c, Field<S> q, CField<S> p, double* partials, const int* done,
          hipStream_t st);
 long hop_nparts(mspcg_ctx* c);
+// traversal tile for a box: the largest even divisor of each extent that does
+// not exceed the preferred tile (all zero: lexicographic order)
+void pick_tile(const int pref[4], const Box& b, int out[4]);
+template <class S>
+int prec_index();
 
 int ensure_partials(mspcg_ctx* c, size_t n);
 
@@ -144,6 +151,10 @@ int precond_apply_flag(mspcg_ctx* c, int l, CField<F64> r, Field<F64> z, const i
                        hipStream_t st);
 template <class S>
 int kblock_apply(mspcg_ctx* c, CField<F64> p_e, Field<F64> q_e, hipStream_t st);
+// w = A_s p on every block (domain layout, precision S)
+template <class S>
+int block_A(mspcg_ctx* c, Field<S> w, CField<S> p, double* partials, const int* done,
+            hipStream_t st);
 
 int solve_one(mspcg_ctx* c, const void* b_dev, void* x_dev, const mspcg_solve_params* p,
               mspcg_solve_stats* stats, hipStream_t st);

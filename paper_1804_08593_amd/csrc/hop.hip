@@ -10,9 +10,25 @@
 // (1 + sig g_mu) psi = [h ; sig e_mu^+ h] with h = psi_up + sig e_mu psi_dn,
 // so only the 2x3 half spinor h is multiplied by the link.
 //   e_x = -i sigma_x, e_y = -i sigma_y, e_z = -i sigma_z, e_t = 1.
+#include <utility>
+
 #include "common.h"
 #include "fived.h"
 #include "kernels.h"
+
+// Build-time variants (measured; the defaults are the fastest on gfx950):
+//   MSPCG_HOP_MINWAVES  occupancy hint of __launch_bounds__
+//   MSPCG_HOP_GROUP     directions whose loads are issued before any is used
+//   MSPCG_HOP_NT        nontemporal link loads and output stores
+#ifndef MSPCG_HOP_MINWAVES
+#define MSPCG_HOP_MINWAVES 1
+#endif
+#ifndef MSPCG_HOP_GROUP
+#define MSPCG_HOP_GROUP 1
+#endif
+#ifndef MSPCG_HOP_NT
+#define MSPCG_HOP_NT true
+#endif
 
 namespace mspcg {
 
@@ -72,26 +88,38 @@ __device__ __forceinline__ void reconstruct(const cx<T> (&w)[6], cx<T> (&acc)[12
     }
 }
 
-// One direction: acc += (1 + SIG g_mu) L in(nbr)
-template <class S, int MU, int SIG>
-__device__ __forceinline__ void hop_dir(const HopArgs<S>& a, long nbr, const typename S::elem* lk,
-                                        long lstride, cx<typename S::real> (&acc)[12]) {
-    using T = typename S::real;
-    cx<T> p[12];
-    load_spinor<S>(a.in, nbr, p);
-    cx<T> h[6];
-    project<MU, SIG>(p, h);
-    cx<T> u[9];
+// Direction D = 0..7: mu = D/2, forward (x+mu) for even D, backward for odd D.
+// Loads of a group of directions are issued together before any of them is
+// used, so a thread keeps several neighbour spinors in flight at once.
+template <class S>
+struct DirData {
+    cx<typename S::real> p[12];
+    cx<typename S::real> u[9];
+    bool ok;
+};
+
+template <class S>
+__device__ __forceinline__ void dir_fetch(const HopArgs<S>& a, long nbr, const typename S::elem* lk,
+                                          long lstride, DirData<S>& dd) {
+    load_spinor<S>(a.in, nbr, dd.p);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) u[k] = load_link<S>(lk + k * lstride);
+    for (int k = 0; k < 9; ++k) dd.u[k] = load_link<S, MSPCG_HOP_NT>(lk + k * lstride);
+}
+
+// acc += (1 + SIG g_mu) U in(nbr)
+template <class S, int MU, int SIG>
+__device__ __forceinline__ void dir_apply(const DirData<S>& dd, cx<typename S::real> (&acc)[12]) {
+    using T = typename S::real;
+    cx<T> h[6];
+    project<MU, SIG>(dd.p, h);
     cx<T> w[6];
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            cx<T> t = cmul(u[i * 3 + 0], h[sp * 3 + 0]);
-            cfma(t, u[i * 3 + 1], h[sp * 3 + 1]);
-            cfma(t, u[i * 3 + 2], h[sp * 3 + 2]);
+            cx<T> t = cmul(dd.u[i * 3 + 0], h[sp * 3 + 0]);
+            cfma(t, dd.u[i * 3 + 1], h[sp * 3 + 1]);
+            cfma(t, dd.u[i * 3 + 2], h[sp * 3 + 2]);
             w[sp * 3 + i] = t;
         }
     reconstruct<MU, SIG>(w, acc);
@@ -114,6 +142,24 @@ __device__ __forceinline__ bool neighbour(const HopGeom& g, const int gc[4], lon
     return true;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (linear id mod 8),
+// each with a private L2.  With remapping, XCD k processes one contiguous
+// range of logical tiles, so neighbouring sites (whose spinors are shared by
+// up to 8 outputs) are fetched into one L2 instead of several.
+__device__ __forceinline__ void logical_block(int remap, int& bx, int& d) {
+    if (!remap) {
+        bx = blockIdx.x;
+        d = blockIdx.y;
+        return;
+    }
+    const unsigned G = gridDim.x, T = G * gridDim.y;
+    const unsigned lid = blockIdx.y * G + blockIdx.x;
+    const unsigned q = T >> 3, r = T & 7, k = lid & 7;
+    const unsigned logical = k * q + (k < r ? k : r) + (lid >> 3);
+    bx = (int)(logical % G);
+    d = (int)(logical / G);
+}
+
 template <class S, int LS>
 __device__ __forceinline__ void block_sum_store(double v, double* dst) {
     __shared__ double red[16];
@@ -129,22 +175,35 @@ __device__ __forceinline__ void block_sum_store(double v, double* dst) {
     }
 }
 
+
+// compile-time loop: f(std::integral_constant<int, i>) for i in [0, N)
+template <class F, int... I>
+__device__ __forceinline__ void sfor_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void sfor(F&& f) {
+    sfor_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 // EPI: the epilogue mixes s (needs the LDS exchange); without it no LDS is
 // allocated, which keeps the occupancy of the plain hop high.
 template <class S, int LS, bool DAG, bool EPI>
-__global__ __launch_bounds__(256) void hop_kernel(HopArgs<S> a) {
+__global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S> a) {
     using T = typename S::real;
     constexpr int SPB = 256 / LS;
     constexpr int SITE_STRIDE = LS * 12 + 1;  // LDS row padding against bank conflicts
     __shared__ cx<T> lds[EPI ? SPB * SITE_STRIDE : 1];
 
     if (a.done && *a.done) return;
-    const int d = blockIdx.y;
+    int bx, d;
+    logical_block(a.xcd_remap, bx, d);
     const int sl = threadIdx.x / LS;
     const int s = threadIdx.x - sl * LS;
-    const long cb = (long)blockIdx.x * SPB + sl;
-    const bool active = sl < SPB && cb < a.g.out.Vh;
+    const long t_lin = (long)bx * SPB + sl;  // position in the traversal order
+    const bool active = sl < SPB && t_lin < a.g.out.Vh;
     const HopGeom& g = a.g;
+    long cb = t_lin;
 
     cx<T> acc[12];
 #pragma unroll
@@ -152,7 +211,30 @@ __global__ __launch_bounds__(256) void hop_kernel(HopArgs<S> a) {
     int gc[4] = {0, 0, 0, 0};
     if (active) {
         int oc[4];
-        box_coords(g.out, cb, g.out_par, oc);
+        if (a.tile[0]) {
+            // 4D-tiled traversal: consecutive workgroups sweep compact tiles of
+            // extent tile[mu] (even, dividing the box), tiles in lex order
+            Box tb;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                tb.E[m] = a.tile[m];
+                tb.off[m] = 0;
+            }
+            const long th = (long)a.tile[0] * a.tile[1] * a.tile[2] * a.tile[3] / 2;
+            long st = t_lin / th;
+            const long w = t_lin - st * th;
+            const int so = g.out.off[0] + g.out.off[1] + g.out.off[2] + g.out.off[3];
+            box_coords(tb, w, (g.out_par + so) & 1, oc);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int nt = g.out.E[m] / a.tile[m];
+                oc[m] += (int)(st % nt) * a.tile[m];
+                st /= nt;
+            }
+            cb = box_cb(g.out, oc);
+        } else {
+            box_coords(g.out, cb, g.out_par, oc);
+        }
 #pragma unroll
         for (int m = 0; m < 4; ++m) gc[m] = oc[m] + g.out.off[m];
         int lc[4];
@@ -166,17 +248,29 @@ __global__ __launch_bounds__(256) void hop_kernel(HopArgs<S> a) {
         // forward terms use (1 - g) and backward (1 + g); the dagger swaps them
         constexpr int SF = DAG ? 1 : -1;
         constexpr int SB = -SF;
-        long n;
-#define MSPCG_DIR(MU)                                                                     \
-    if (neighbour<MU, 1>(g, gc, n))                                                        \
-        hop_dir<S, MU, SF>(a, (ibase + n) * LS + s, lbase + (MU)*9 * lstride, lstride, acc); \
-    if (neighbour<MU, 0>(g, gc, n))                                                        \
-        hop_dir<S, MU, SB>(a, (ibase + n) * LS + s, lbase + (4 + (MU)) * 9 * lstride, lstride, acc);
-        MSPCG_DIR(0)
-        MSPCG_DIR(1)
-        MSPCG_DIR(2)
-        MSPCG_DIR(3)
-#undef MSPCG_DIR
+        // directions in groups of MSPCG_HOP_GROUP: fetch all, then apply all
+        constexpr int GRP = MSPCG_HOP_GROUP;
+        static_assert(8 % GRP == 0, "group must divide 8");
+        sfor<8 / GRP>([&](auto gi) {
+            constexpr int G0 = decltype(gi)::value * GRP;
+            DirData<S> dd[GRP];
+            sfor<GRP>([&](auto j) {
+                constexpr int D = G0 + decltype(j)::value;
+                constexpr int MU = D / 2;
+                constexpr bool FWD = (D % 2) == 0;
+                long n = 0;
+                dd[j].ok = neighbour<MU, FWD ? 1 : 0>(g, gc, n);
+                if (dd[j].ok)
+                    dir_fetch<S>(a, (ibase + n) * LS + s, lbase + (FWD ? MU : 4 + MU) * 9 * lstride,
+                                 lstride, dd[j]);
+            });
+            sfor<GRP>([&](auto j) {
+                constexpr int D = G0 + decltype(j)::value;
+                constexpr int MU = D / 2;
+                constexpr bool FWD = (D % 2) == 0;
+                if (dd[j].ok) dir_apply<S, MU, FWD ? SF : SB>(dd[j], acc);
+            });
+        });
     }
 
     const long oidx = ((long)d * g.out.Vh + cb) * LS + s;
@@ -256,7 +350,7 @@ __global__ __launch_bounds__(256) void hop_kernel(HopArgs<S> a) {
         }
     }
 
-    if (active) store_spinor<S>(a.out, oidx, res);
+    if (active) store_spinor<S, MSPCG_HOP_NT>(a.out, oidx, res);
     if (a.partials) {
         double n2 = 0;
         if (active) {
@@ -265,7 +359,7 @@ __global__ __launch_bounds__(256) void hop_kernel(HopArgs<S> a) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) n2 += (double)res[c].re * res[c].re + (double)res[c].im * res[c].im;
         }
-        block_sum_store<S, LS>(n2, a.partials + (long)d * gridDim.x + blockIdx.x);
+        block_sum_store<S, LS>(n2, a.partials + (long)d * gridDim.x + bx);
     }
 }
 

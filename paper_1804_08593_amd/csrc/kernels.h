@@ -31,6 +31,8 @@ struct HopArgs {
     double mf;
     double* partials;  // optional: per (domain, workgroup) sum |out|^2
     const int* done;   // optional: skip the launch when *done != 0
+    int xcd_remap;     // map workgroups so each XCD walks a contiguous site range
+    int tile[4];       // nonzero: traverse output sites in 4D tiles of this extent
 };
 
 template <class S>

@@ -303,6 +303,8 @@ static int dom_hop(mspcg_ctx* c, Field<S> out, const Box& bout, CField<S> in, co
     a.mf = c->act.mf;
     a.partials = partials;
     a.done = done;
+    a.xcd_remap = c->tune.xcd_remap;
+    pick_tile(c->tune.tile[prec_index<S>()], bout, a.tile);
     const double bytes = (double)D.ndom * c->Ls *
                              (double)(bout.Vh + bin.Vh + (aux ? baux.Vh : 0)) * S::bytes_spinor +
                          (double)D.ndom * bout.Vh * 8 * S::bytes_link;
@@ -329,8 +331,8 @@ static int dom_fived(mspcg_ctx* c, Field<S> out, CField<S> in, long Vh, const Fi
 // partials (optional) receive per-domain |Mhat_D p|^2 = <p, A_s p>, laid out
 // [ndom][hop_grid_x(pad2.Vh)].
 template <class S>
-static int block_A(mspcg_ctx* c, Field<S> w, CField<S> p, double* partials, const int* done,
-                   hipStream_t st) {
+int block_A(mspcg_ctx* c, Field<S> w, CField<S> p, double* partials, const int* done,
+            hipStream_t st) {
     const Domains& D = c->dom;
     const int Ls = c->Ls;
     const std::string pf = std::string("dom") + (std::is_same<S, F16>::value ? "16." : std::is_same<S, F32>::value ? "32." : "64.");
@@ -480,6 +482,10 @@ int kblock_apply(mspcg_ctx* c, CField<F64> p_e, Field<F64> q_e, hipStream_t st) 
         return MSPCG_EHIP;
     return 0;
 }
+
+template int block_A<F64>(mspcg_ctx*, Field<F64>, CField<F64>, double*, const int*, hipStream_t);
+template int block_A<F32>(mspcg_ctx*, Field<F32>, CField<F32>, double*, const int*, hipStream_t);
+template int block_A<F16>(mspcg_ctx*, Field<F16>, CField<F16>, double*, const int*, hipStream_t);
 
 #define MSPCG_PC(S)                                                                         \
     template int precond_apply<S>(mspcg_ctx*, int, CField<F64>, Field<F64>, hipStream_t,   \

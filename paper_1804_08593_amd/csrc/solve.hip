@@ -419,13 +419,19 @@ int solve_one(mspcg_ctx* c, const void* b_dev, void* x_dev, const mspcg_solve_pa
     if (launch_pack_parity<F64>(b, bo, c->L, c->Ls, 1, st)) return MSPCG_EHIP;
     if (p->use_x0 && launch_pack_parity<F64>((const double2*)x_dev, xe, c->L, c->Ls, 0, st))
         return MSPCG_EHIP;
-    // b'_e = b_e + (1/2) D_h^eo X b_o ; bhat = Mhat^+ b'_e
     CField<F64> ae = cfield(be);
-    if ((e = op_fived<F64>(c, w, cfield(bo), P.X, nullptr, nullptr, st))) return e;
-    if ((e = op_hop<F64>(c, bp, cfield(w), 0, false, scaled(P.id, 0.5, 0.5), &ae, P.id, nullptr,
-                         nullptr, st)))
-        return e;
-    if ((e = op_mhatdag<F64>(c, bhat, cfield(bp), nullptr, st))) return e;
+    if (p->rhs_normal) {
+        // the right-hand side of A x = bhat is given directly
+        MSPCG_HIP(hipMemcpyAsync(bhat.data, be.data, (size_t)12 * c->Nh * sizeof(double2),
+                                 hipMemcpyDeviceToDevice, st));
+    } else {
+        // b'_e = b_e + (1/2) D_h^eo X b_o ; bhat = Mhat^+ b'_e
+        if ((e = op_fived<F64>(c, w, cfield(bo), P.X, nullptr, nullptr, st))) return e;
+        if ((e = op_hop<F64>(c, bp, cfield(w), 0, false, scaled(P.id, 0.5, 0.5), &ae, P.id, nullptr,
+                             nullptr, st)))
+            return e;
+        if ((e = op_mhatdag<F64>(c, bhat, cfield(bp), nullptr, st))) return e;
+    }
     double bb;
     if ((e = norm2_sync(c, bhat.data, nullptr, st, bb))) return e;
     int rc;
@@ -451,16 +457,20 @@ int solve_one(mspcg_ctx* c, const void* b_dev, void* x_dev, const mspcg_solve_pa
             rc = mspcg_fp64<F64>(c, cfield(bhat), xe, p->use_x0 != 0, p, bb, stats, st);
         if (rc != MSPCG_OK && rc != MSPCG_ENOCONV) return rc;
     }
-    // x_o = M5op^-1 (b_o + (1/2) D_h^oe B x_e)
-    Field<F64> te = w;
-    CField<F64> ao = cfield(bo);
-    if ((e = op_fived<F64>(c, te, cfield(xe), P.B, nullptr, nullptr, st))) return e;
-    if ((e = op_hop<F64>(c, xo, cfield(te), 1, false, scaled(P.M5inv, 0.5, 0.5), &ao, P.M5inv,
-                         nullptr, nullptr, st)))
-        return e;
     double2* x = (double2*)x_dev;
-    if (launch_unpack_parity<F64>(cfield(xe), x, c->L, c->Ls, 0, 0, st)) return MSPCG_EHIP;
-    if (launch_unpack_parity<F64>(cfield(xo), x, c->L, c->Ls, 1, 0, st)) return MSPCG_EHIP;
+    if (p->rhs_normal) {
+        if (launch_unpack_parity<F64>(cfield(xe), x, c->L, c->Ls, 0, 1, st)) return MSPCG_EHIP;
+    } else {
+        // x_o = M5op^-1 (b_o + (1/2) D_h^oe B x_e)
+        Field<F64> te = w;
+        CField<F64> ao = cfield(bo);
+        if ((e = op_fived<F64>(c, te, cfield(xe), P.B, nullptr, nullptr, st))) return e;
+        if ((e = op_hop<F64>(c, xo, cfield(te), 1, false, scaled(P.M5inv, 0.5, 0.5), &ao, P.M5inv,
+                             nullptr, nullptr, st)))
+            return e;
+        if (launch_unpack_parity<F64>(cfield(xe), x, c->L, c->Ls, 0, 0, st)) return MSPCG_EHIP;
+        if (launch_unpack_parity<F64>(cfield(xo), x, c->L, c->Ls, 1, 0, st)) return MSPCG_EHIP;
+    }
     MSPCG_HIP(hipEventRecord(e1, st));
     MSPCG_HIP(hipStreamSynchronize(st));
     const auto wall1 = std::chrono::steady_clock::now();

@@ -24,7 +24,8 @@ KC_NAMES = ("hop64", "hop32", "hopdom", "fived", "blas")
 KC_COUNT = 5
 EXPORTS = ("mspcg_create", "mspcg_destroy", "mspcg_strerror", "mspcg_version",
            "mspcg_load_gauge", "mspcg_apply", "mspcg_set_blocking", "mspcg_precond",
-           "mspcg_solve", "mspcg_solve_batch", "mspcg_force")
+           "mspcg_solve", "mspcg_solve_batch", "mspcg_force", "mspcg_get_tuning",
+           "mspcg_set_tuning", "mspcg_autotune")
 
 
 class MspcgError(RuntimeError):
@@ -43,11 +44,20 @@ class Blocking(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int * 4), ("pad", ctypes.c_int)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("xcd_remap", ctypes.c_int), ("tile", (ctypes.c_int * 4) * 3)]
+
+    def as_dict(self):
+        return {"xcd_remap": self.xcd_remap,
+                "tile": {n: list(self.tile[i]) for i, n in enumerate(("fp64", "fp32", "fp16"))}}
+
+
 class SolveParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("solver", ctypes.c_int),
                 ("use_x0", ctypes.c_int), ("blocking", Blocking), ("inner_iters", ctypes.c_int),
                 ("inner_prec", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("delta", ctypes.c_double), ("timing", ctypes.c_int)]
+                ("delta", ctypes.c_double), ("timing", ctypes.c_int),
+                ("rhs_normal", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
@@ -92,7 +102,10 @@ def load(path: str = LIB_PATH):
         lib.mspcg_solve_batch.argtypes = [ctypes.POINTER(P), I, ctypes.POINTER(P),
                                           ctypes.POINTER(P), ctypes.POINTER(SolveParams),
                                           ctypes.POINTER(SolveStats), P]
-        lib.mspcg_force.argtypes = [P, P, P, P, P]
+        lib.mspcg_force.argtypes = [P, P, P, P, P, P]
+        lib.mspcg_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+        lib.mspcg_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+        lib.mspcg_autotune.argtypes = [P, ctypes.POINTER(Blocking), ctypes.c_char_p, P]
         _lib = lib
     return _lib
 
@@ -123,7 +136,7 @@ def _ptr(t):
 
 def make_params(tol=1e-10, maxiter=10000, solver=SOLVER_CG, use_x0=False, block=(0, 0, 0, 0),
                 pad=2, inner_iters=6, inner_prec=FP16, check_every=0, delta=0.1,
-                timing=False) -> SolveParams:
+                timing=False, rhs_normal=False) -> SolveParams:
     p = SolveParams()
     p.tol, p.maxiter, p.solver, p.use_x0 = float(tol), int(maxiter), int(solver), int(use_x0)
     for i in range(4):
@@ -131,6 +144,7 @@ def make_params(tol=1e-10, maxiter=10000, solver=SOLVER_CG, use_x0=False, block=
     p.blocking.pad = int(pad)
     p.inner_iters, p.inner_prec = int(inner_iters), int(inner_prec)
     p.check_every, p.delta, p.timing = int(check_every), float(delta), int(timing)
+    p.rhs_normal = int(bool(rhs_normal))
     return p
 
 
@@ -207,10 +221,38 @@ class Context:
         _check(rc, "mspcg_solve", allow=(ENOCONV,) if allow_noconv else ())
         return stats_dict(st, hist, rc)
 
-    def force(self, X, Y, F, stream=None):
-        _check(load().mspcg_force(self._h, _ptr(X), _ptr(Y), _ptr(F), _stream(stream)),
+    def get_tuning(self) -> Tuning:
+        t = Tuning()
+        _check(load().mspcg_get_tuning(self._h, ctypes.byref(t)), "mspcg_get_tuning")
+        return t
+
+    def set_tuning(self, xcd_remap=1, fp64=(0, 0, 0, 0), fp32=(0, 0, 0, 0), fp16=(0, 0, 0, 0)):
+        t = Tuning()
+        t.xcd_remap = int(xcd_remap)
+        for i, tl in enumerate((fp64, fp32, fp16)):
+            for m in range(4):
+                t.tile[i][m] = int(tl[m])
+        _check(load().mspcg_set_tuning(self._h, ctypes.byref(t)), "mspcg_set_tuning")
+
+    def autotune(self, block=None, pad=2, cache_path=None, stream=None) -> dict:
+        b = None
+        if block is not None:
+            b = Blocking()
+            for i in range(4):
+                b.block[i] = int(block[i])
+            b.pad = int(pad)
+        _check(load().mspcg_autotune(self._h, ctypes.byref(b) if b is not None else None,
+                                     cache_path.encode() if cache_path else None,
+                                     _stream(stream)), "mspcg_autotune")
+        return self.get_tuning().as_dict()
+
+    def force(self, X, Y, F=None, G=None, stream=None):
+        """F: traceless Hermitian force per link; G: gradient w.r.t. the complex link."""
+        _check(load().mspcg_force(self._h, _ptr(X), _ptr(Y),
+                                  _ptr(F) if F is not None else None,
+                                  _ptr(G) if G is not None else None, _stream(stream)),
                "mspcg_force")
-        return F
+        return F, G
 
 
 def stats_dict(st: SolveStats, hist=None, rc=OK) -> dict:

@@ -65,6 +65,8 @@ def test_null_pointers_rejected():
     assert lib.mspcg_create(None, 0, None) == mspcg.EINVAL
     assert lib.mspcg_apply(None, 0, 0, None, None, None) == mspcg.EINVAL
     assert lib.mspcg_solve(None, None, None, None, None, None) == mspcg.EINVAL
-    assert lib.mspcg_force(None, None, None, None, None) == mspcg.EINVAL
+    assert lib.mspcg_force(None, None, None, None, None, None) == mspcg.EINVAL
+    assert lib.mspcg_autotune(None, None, None, None) == mspcg.EINVAL
+    assert lib.mspcg_get_tuning(None, None) == mspcg.EINVAL
     assert lib.mspcg_load_gauge(None, None, None) == mspcg.EINVAL
     lib.mspcg_destroy(None)
