@@ -123,7 +123,8 @@ typedef struct {
     int maxiter;          /* outer iterations */
     int solver;           /* MSPCG_SOLVER_* */
     int use_x0;           /* 1: x holds the initial guess on entry (even part used) */
-    mspcg_blocking blocking; /* MSPCG only */
+    mspcg_blocking blocking; /* MSPCG only; block[0] == 0: the context's blocking
+                                (mspcg_set_blocking) is used */
     int inner_iters;      /* l: local CG iterations per outer iteration (MSPCG) */
     int inner_prec;       /* MSPCG_FP16 / FP32 / FP64 for the local solves (MSPCG) */
     int check_every;      /* host convergence poll interval in iterations (0: auto) */
@@ -220,6 +221,15 @@ int mspcg_set_tuning(mspcg_ctx* ctx, const mspcg_tuning* tuning);
  * NULL (read first, appended after tuning).  Needs the gauge field. */
 int mspcg_autotune(mspcg_ctx* ctx, const mspcg_blocking* blocking, const char* cache_path,
                    hipStream_t stream);
+
+/* Block-shape autotuner for MSPCG (the blocks play the role of the paper's
+ * nodes, Sec. 3): for each candidate blocking (halving the longest directions,
+ * or quartering long ones), runs probe_iters outer iterations of MSPCG with
+ * base's local-solve settings on a fixed synthetic right-hand side and keeps
+ * the blocking with the fastest residual reduction per second.  The choice
+ * becomes the context's blocking and is returned in chosen (may be NULL). */
+int mspcg_tune_blocking(mspcg_ctx* ctx, const mspcg_solve_params* base, int probe_iters,
+                        mspcg_blocking* chosen, hipStream_t stream);
 
 /* HMC fermion force of S = phi^+ A^-1 phi (the solve inside ensemble
  * generation, Sec. 1.1).  X = A^-1 phi and Y = Mhat X are even fields.

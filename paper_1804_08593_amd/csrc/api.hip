@@ -584,7 +584,5 @@ extern "C" int mspcg_solve_batch(mspcg_ctx* const* ctxs, int n, const void* cons
                                  void* const* x_dev, const mspcg_solve_params* p,
                                  mspcg_solve_stats* stats, hipStream_t st) {
     if (!ctxs || n < 0 || !b_dev || !x_dev || !p) return MSPCG_EINVAL;
-    (void)stats;
-    (void)st;
-    return MSPCG_EUNSUPPORTED;
+    return solve_batch(ctxs, n, b_dev, x_dev, p, stats, st);
 }

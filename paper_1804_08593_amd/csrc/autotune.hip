@@ -2,6 +2,7 @@
 // remap on the context's own lattice (A in FP64 / FP32, the block operator
 // in the local-solve precision) with HIP events, keeps the fastest, and
 // caches the choice per (dims, Ls, blocking) in a plain text file.
+#include <math.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -177,5 +178,105 @@ extern "C" int mspcg_autotune(mspcg_ctx* c, const mspcg_blocking* bk, const char
     c->tune = t;
     c->timing = was_timing;
     if (cache_path) cache_store(cache_path, key, t);
+    return MSPCG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Block-shape selection for MSPCG
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// deterministic pseudo-random fill in [-1, 1) (SplitMix64 of the index)
+__global__ void fill_hash_kernel(double* p, long n, unsigned long long seed) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    unsigned long long z = seed + 0x9E3779B97F4A7C15ull * (unsigned long long)(i + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    p[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+std::vector<mspcg_blocking> block_candidates(const mspcg_ctx* c, int pad) {
+    std::vector<mspcg_blocking> v;
+    auto ok = [&](int L, int b) { return b >= 2 && !(b & 1) && L % b == 0 && (L == b || L - b >= 2 * pad); };
+    // halve the k longest directions (k = 1..4), and quarter every direction when possible
+    int order[4] = {0, 1, 2, 3};
+    for (int i = 0; i < 4; ++i)
+        for (int j = i + 1; j < 4; ++j)
+            if (c->L[order[j]] > c->L[order[i]]) std::swap(order[i], order[j]);
+    for (int k = 1; k <= 4; ++k) {
+        mspcg_blocking b;
+        b.pad = pad;
+        bool good = true;
+        for (int m = 0; m < 4; ++m) b.block[m] = c->L[m];
+        for (int i = 0; i < k; ++i) {
+            const int m = order[i];
+            b.block[m] = c->L[m] / 2;
+            good = good && ok(c->L[m], b.block[m]);
+        }
+        if (good) v.push_back(b);
+    }
+    mspcg_blocking q;
+    q.pad = pad;
+    bool good = true;
+    for (int m = 0; m < 4; ++m) {
+        q.block[m] = c->L[m] >= 16 ? c->L[m] / 4 : c->L[m] / 2;
+        good = good && ok(c->L[m], q.block[m]);
+    }
+    if (good) v.push_back(q);
+    return v;
+}
+
+}  // namespace
+
+extern "C" int mspcg_tune_blocking(mspcg_ctx* c, const mspcg_solve_params* base, int probe_iters,
+                                   mspcg_blocking* chosen, hipStream_t st) {
+    if (!c || !base || probe_iters < 1) return MSPCG_EINVAL;
+    if (!c->gauge) return MSPCG_ENOGAUGE;
+    MSPCG_HIP(hipSetDevice(c->device));
+    const int pad = base->blocking.pad > 0 || base->blocking.block[0] ? base->blocking.pad : 2;
+    std::vector<mspcg_blocking> cands = block_candidates(c, pad);
+    if (cands.empty()) return MSPCG_EUNSUPPORTED;
+    const size_t n = (size_t)c->V4 * c->Ls * 12;
+    double2* b = (double2*)c->buf("tb.b", n * sizeof(double2));
+    double2* x = (double2*)c->buf("tb.x", n * sizeof(double2));
+    if (!b || !x) return MSPCG_ENOMEM;
+    hipLaunchKernelGGL(fill_hash_kernel, dim3((unsigned)((2 * n + 255) / 256)), dim3(256), 0, st,
+                       (double*)b, (long)(2 * n), 12345ull);
+    if (hipGetLastError() != hipSuccess) return MSPCG_EHIP;
+    mspcg_solve_params p = *base;
+    p.solver = MSPCG_SOLVER_MSPCG;
+    p.maxiter = probe_iters;
+    p.tol = 1e-300;
+    p.use_x0 = 0;
+    p.timing = 0;
+    p.rhs_normal = 0;
+    double best = -1;
+    mspcg_blocking bestb = cands[0];
+    std::vector<double> hist(probe_iters + 1);
+    for (const mspcg_blocking& cb : cands) {
+        p.blocking = cb;
+        mspcg_solve_stats s;
+        memset(&s, 0, sizeof(s));
+        s.resid_history = hist.data();
+        s.resid_history_cap = probe_iters;
+        int e = solve_one(c, b, x, &p, &s, st);  // first run also builds the domain links
+        if (e != MSPCG_OK && e != MSPCG_ENOCONV) return e;
+        e = solve_one(c, b, x, &p, &s, st);
+        if (e != MSPCG_OK && e != MSPCG_ENOCONV) return e;
+        if (s.resid_history_len < 1 || !(s.seconds > 0)) continue;
+        const double r = hist[s.resid_history_len - 1];
+        if (!(r > 0)) continue;
+        const double rate = -log(r) / s.seconds;  // e-folds of residual per second
+        if (rate > best) {
+            best = rate;
+            bestb = cb;
+        }
+    }
+    c->blocking = bestb;
+    c->has_blocking = true;
+    if (chosen) *chosen = bestb;
     return MSPCG_OK;
 }

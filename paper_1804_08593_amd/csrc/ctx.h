@@ -158,5 +158,7 @@ int block_A(mspcg_ctx* c, Field<S> w, CField<S> p, double* partials, const int* 
 
 int solve_one(mspcg_ctx* c, const void* b_dev, void* x_dev, const mspcg_solve_params* p,
               mspcg_solve_stats* stats, hipStream_t st);
+int solve_batch(mspcg_ctx* const* cs, int n, const void* const* b, void* const* x,
+                const mspcg_solve_params* p, mspcg_solve_stats* stats, hipStream_t st);
 
 }  // namespace mspcg

@@ -25,7 +25,7 @@ KC_COUNT = 5
 EXPORTS = ("mspcg_create", "mspcg_destroy", "mspcg_strerror", "mspcg_version",
            "mspcg_load_gauge", "mspcg_apply", "mspcg_set_blocking", "mspcg_precond",
            "mspcg_solve", "mspcg_solve_batch", "mspcg_force", "mspcg_get_tuning",
-           "mspcg_set_tuning", "mspcg_autotune")
+           "mspcg_set_tuning", "mspcg_autotune", "mspcg_tune_blocking")
 
 
 class MspcgError(RuntimeError):
@@ -106,6 +106,8 @@ def load(path: str = LIB_PATH):
         lib.mspcg_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
         lib.mspcg_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
         lib.mspcg_autotune.argtypes = [P, ctypes.POINTER(Blocking), ctypes.c_char_p, P]
+        lib.mspcg_tune_blocking.argtypes = [P, ctypes.POINTER(SolveParams), I,
+                                            ctypes.POINTER(Blocking), P]
         _lib = lib
     return _lib
 
@@ -246,6 +248,14 @@ class Context:
                                      _stream(stream)), "mspcg_autotune")
         return self.get_tuning().as_dict()
 
+    def tune_blocking(self, params: "SolveParams" = None, probe_iters=8, stream=None):
+        """Pick the MSPCG block shape with the fastest residual reduction per second."""
+        p = params if params is not None else make_params(solver=SOLVER_MSPCG)
+        b = Blocking()
+        _check(load().mspcg_tune_blocking(self._h, ctypes.byref(p), int(probe_iters),
+                                          ctypes.byref(b), _stream(stream)), "mspcg_tune_blocking")
+        return tuple(b.block), b.pad
+
     def force(self, X, Y, F=None, G=None, stream=None):
         """F: traceless Hermitian force per link; G: gradient w.r.t. the complex link."""
         _check(load().mspcg_force(self._h, _ptr(X), _ptr(Y),
@@ -273,12 +283,21 @@ def stats_dict(st: SolveStats, hist=None, rc=OK) -> dict:
     return d
 
 
-def solve_batch(ctxs, bs, xs, params: SolveParams, stream=None):
+def solve_batch(ctxs, bs, xs, params: SolveParams, history=0, stream=None, allow_noconv=False):
+    """Solve n independent systems together (hipGraph-replayed outer iterations)."""
     n = len(ctxs)
     H = (ctypes.c_void_p * n)(*[c.handle for c in ctxs])
     B = (ctypes.c_void_p * n)(*[_ptr(b) for b in bs])
     X = (ctypes.c_void_p * n)(*[_ptr(x) for x in xs])
     sts = (SolveStats * n)()
+    hists = []
+    for i in range(n):
+        h = None
+        if history:
+            h = (ctypes.c_double * int(history))()
+            sts[i].resid_history = ctypes.cast(h, ctypes.POINTER(ctypes.c_double))
+            sts[i].resid_history_cap = int(history)
+        hists.append(h)
     rc = load().mspcg_solve_batch(H, n, B, X, ctypes.byref(params), sts, _stream(stream))
-    _check(rc, "mspcg_solve_batch")
-    return [stats_dict(sts[i]) for i in range(n)]
+    _check(rc, "mspcg_solve_batch", allow=(ENOCONV,) if allow_noconv else ())
+    return [stats_dict(sts[i], hists[i], rc) for i in range(n)]
