@@ -3,7 +3,8 @@ residual on one MI355X.
 
 A step is one pass of the whole hot path on the 24^3x48, Ls=16 Moebius
 workload (b=1.5, c=0.5, M5=1.8, mf=0.005, links exp(0.2 i H)): the even-odd
-RHS preparation, a plain FP64 CG solve to a true residual of 1e-10, an MSPCG
+RHS preparation, a plain FP64 CG solve to a true residual of 1e-10, a
+mixed-precision CG solve (FP32 iterations, FP64 reliable updates), an MSPCG
 solve (16 blocks of 12^3x24, 6 local iterations, FP16 storage / FP32 math)
 to the same residual, and the odd-site reconstruction.  Inputs are seeded
 synthetic fields already resident in HBM when the timed region starts.
@@ -100,6 +101,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-mspcg", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--inner-iters", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--calibrate", action="store_true",
@@ -139,28 +142,34 @@ def main():
 
     p_cg = mspcg.make_params(tol=args.tol, maxiter=20000, solver=mspcg.SOLVER_CG, timing=True)
     p_ms = mspcg.make_params(tol=args.tol, maxiter=20000, solver=mspcg.SOLVER_MSPCG,
-                             block=w["block"], pad=2, inner_iters=6, inner_prec=mspcg.FP16,
-                             timing=True)
+                             block=w["block"], pad=2, inner_iters=args.inner_iters,
+                             inner_prec=mspcg.FP16, timing=True)
+    p_mx = mspcg.make_params(tol=args.tol, maxiter=20000, solver=mspcg.SOLVER_MIXED_CG,
+                             delta=0.1, timing=True)
     run_ms = not args.no_mspcg
+    run_mx = not args.no_mixed
 
     def step():
         out = {"cg": ctx.solve(bd, x, p_cg)}
+        if run_mx:
+            out["mixed"] = ctx.solve(bd, x, p_mx)
         if run_ms:
             out["mspcg"] = ctx.solve(bd, x, p_ms)
         return out
 
+    def describe(r):
+        return ", ".join(f"{k} {v['outer_iters']} it {v['seconds']:.3f} s" for k, v in r.items())
+
     for i in range(args.warmup):
         r = step()
-        log(f"[bench] warmup {i}: cg {r['cg']['outer_iters']} it {r['cg']['seconds']:.3f} s"
-            + (f", mspcg {r['mspcg']['outer_iters']} it {r['mspcg']['seconds']:.3f} s" if run_ms else ""))
+        log(f"[bench] warmup {i}: {describe(r)}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
     for i in range(args.steps):
         r = step()
         results.append(r)
-        log(f"[bench] step {i}: cg {r['cg']['outer_iters']} it {r['cg']['seconds']:.3f} s"
-            + (f", mspcg {r['mspcg']['outer_iters']} it {r['mspcg']['seconds']:.3f} s" if run_ms else ""))
+        log(f"[bench] step {i}: {describe(r)}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
@@ -196,7 +205,7 @@ def main():
         "data": "synthetic (seeded exp(i eps H) links, Gaussian RHS)",
         "config": {"workload": args.workload, "dims": list(dims), "Ls": Ls, "M5": w["M5"],
                    "mf": w["mf"], "b": w["b"], "c": w["c"], "block": list(w["block"]),
-                   "inner_iters": 6, "tol": args.tol},
+                   "inner_iters": args.inner_iters, "tol": args.tol},
         "cg": {"seconds": round(cg_s, 4), "outer_iters": last["cg"]["outer_iters"],
                "true_rel_resid": last["cg"]["true_rel_resid"]},
         "kernels": per_class,
@@ -205,6 +214,12 @@ def main():
                      "frac": round(dom_gbs / HBM_PEAK_GBS, 4) if dom_gbs else None,
                      "traffic": measured_traffic(args.workload) if dom == "hop64" else None},
     }
+    if run_mx:
+        mx_s = float(np.median([r["mixed"]["seconds"] for r in results]))
+        line["mixed_cg"] = {"seconds": round(mx_s, 4), "outer_iters": last["mixed"]["outer_iters"],
+                            "reliable_updates": last["mixed"]["restarts"],
+                            "true_rel_resid": last["mixed"]["true_rel_resid"],
+                            "speedup_vs_cg": round(cg_s / mx_s, 3)}
     if run_ms:
         ms_s = float(np.median([r["mspcg"]["seconds"] for r in results]))
         line["mspcg"] = {"seconds": round(ms_s, 4), "outer_iters": last["mspcg"]["outer_iters"],
