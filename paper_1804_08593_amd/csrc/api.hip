@@ -125,6 +125,7 @@ template <class S>
 Field<S> half_field(mspcg_ctx* c, const std::string& name, long N) {
     Field<S> f;
     f.N = N;
+    f.ls = c->Ls;
     f.data = (typename S::elem*)c->buf(name, (size_t)N * 12 * sizeof(typename S::elem));
     f.scale = S::has_scale ? (float*)c->buf(name + ".scale", (size_t)N * sizeof(float)) : nullptr;
     return f;

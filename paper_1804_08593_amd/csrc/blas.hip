@@ -37,10 +37,10 @@ __global__ __launch_bounds__(256) void fived_kernel(FiveDArgs<S> a) {
     const int s = threadIdx.x - sl * LS;
     const long cb = (long)blockIdx.x * SPB + sl;
     const bool active = sl < SPB && cb < a.Vh;
-    const long idx = ((long)d * a.Vh + cb) * LS + s;
+    const long ib = ((long)d * a.Vh + cb) * LS;
     cx<T> v[12];
     if (active) {
-        load_spinor<S>(a.in, idx, v);
+        load_spinor_at<S>(a.in, ib, s, LS, v);
 #pragma unroll
         for (int c = 0; c < 12; ++c) lds[sl * SITE_STRIDE + s * 12 + c] = v[c];
     }
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void fived_kernel(FiveDArgs<S> a) {
             v[c] = lds[sl * SITE_STRIDE + s * 12 + c];
             n2 += (double)v[c].re * v[c].re + (double)v[c].im * v[c].im;
         }
-        store_spinor<S>(a.out, idx, v);
+        store_spinor_at<S>(a.out, ib, s, LS, v);
     }
     if (a.partials) block_reduce_store(n2, a.partials + (long)d * gridDim.x + blockIdx.x);
 }
@@ -270,16 +270,23 @@ __global__ void xpay32_kernel(float2* p, const float2* r, long n, const DevScala
     }
 }
 
-// x (FP64) += xs (FP32); xs = 0
-__global__ void accum32_kernel(double2* x, float2* xs, long n) {
+// x (FP64) += xs (FP32); xs = 0.  Both are site-blocked with 16-byte chunks,
+// so FP64 element (site, c, s) at (site*12 + c)*Ls + s pairs with FP32
+// element (site*6 + c/2)*2*Ls + 2*s + c%2.
+__global__ void accum32_kernel(double2* x, float2* xs, long n, int Ls) {
+    const long per_site = 12L * Ls;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long)gridDim.x * blockDim.x) {
-        const float2 v = xs[i];
+        const long site = i / per_site;
+        const int r = (int)(i - site * per_site);
+        const int c = r / Ls, s = r - c * Ls;
+        const long j = site * per_site + (long)(c >> 1) * 2 * Ls + 2 * s + (c & 1);
+        const float2 v = xs[j];
         double2 xv = x[i];
         xv.x += (double)v.x;
         xv.y += (double)v.y;
         x[i] = xv;
-        xs[i] = make_float2(0.f, 0.f);
+        xs[j] = make_float2(0.f, 0.f);
     }
 }
 
@@ -300,9 +307,9 @@ int launch_xpay32(float2* p, const float2* r, long N, const DevScalars* sc, hipS
     return last_error();
 }
 
-int launch_accum32(double2* x, float2* xs, long N, hipStream_t st) {
+int launch_accum32(double2* x, float2* xs, long N, int Ls, hipStream_t st) {
     hipLaunchKernelGGL(accum32_kernel, dim3((unsigned)blas_grid_x(12 * N)), dim3(kThreads), 0, st,
-                       x, xs, 12 * N);
+                       x, xs, 12 * N, Ls);
     return last_error();
 }
 

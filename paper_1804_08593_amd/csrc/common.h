@@ -6,16 +6,20 @@
 //     special case of one domain whose boxes are the lattice itself.
 //   * Sites of one parity in a box are numbered by cb = lex/2 with
 //     lex = ((t*E2 + z)*E1 + y)*E0 + x (E0 even).
-//   * Spinor fields are structure-of-arrays over 12 complex components:
-//     element (comp, domain d, cb, s) lives at comp*N + (d*Vh + cb)*Ls + s,
-//     N = ndomains*Vh*Ls.  A thread owns one (site, s) and consecutive lanes
-//     hold consecutive s, so every component access of a wave is contiguous.
+//   * Spinor fields are site-blocked: entry i = site*Ls + s (site = d*Vh + cb
+//     for domain fields) keeps its 12 complex components in 16-byte chunks of
+//     V = 16/sizeof(elem) components (V = 1, 2, 4 for FP64, FP32, FP16), and
+//     chunk k of (site, s) is chunk number (site*K + k)*Ls + s of the array,
+//     K = 12/V.  A thread owns one (site, s); consecutive lanes hold
+//     consecutive s, so every chunk access of a wave is contiguous, and a
+//     spinor costs K vector loads of 16 bytes per lane whatever the precision.
 //   * FP16 fields store value/scale as __half2 per complex component plus one
-//     FP32 scale per (site, s) (the max |real| over its 24 reals).
-//   * Links are stored per output parity and per direction as
-//     [parity][8][9][Vh_linkbox]: dirs 0..3 hold U_mu(x), dirs 4..7 hold
+//     FP32 scale per entry (the max |real| over its 24 reals), scale[i].
+//   * Links are stored per output parity and link-box site as
+//     [parity][Vh_linkbox][8][9]: dirs 0..3 hold U_mu(x), dirs 4..7 hold
 //     U_mu(x-mu)^+ (already daggered), with the antiperiodic-time sign folded
-//     in.  Each link is read once per site and reused by all Ls lanes.
+//     in.  The 72 entries of a site are contiguous so a workgroup stages them
+//     with a few coalesced 16-byte loads and all Ls lanes reuse them.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
@@ -65,12 +69,13 @@ struct F16 {
     static constexpr int bytes_link = 36;
 };
 
-// A field: 12 component arrays of N elements (+ scales for FP16).
+// A field of N entries (site, s) with `ls` entries per site (+ scales for FP16).
 template <class S>
 struct Field {
     typename S::elem* data;
     float* scale;  // FP16 only
-    long N;        // elements per component
+    long N;        // entries (site, s)
+    int ls;        // entries per site (the Ls of the field)
 };
 
 template <class S>
@@ -78,84 +83,137 @@ struct CField {
     const typename S::elem* data;
     const float* scale;
     long N;
+    int ls;
 };
 
 template <class S>
 __host__ __device__ inline CField<S> cfield(Field<S> f) {
-    return {f.data, f.scale, f.N};
+    return {f.data, f.scale, f.N, f.ls};
+}
+
+// 16-byte chunk types of the site-blocked layout
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef unsigned nt_u4 __attribute__((ext_vector_type(4)));
+
+template <class S>
+struct Chunk {
+    static constexpr int V = 16 / (int)sizeof(typename S::elem);  // components per chunk
+    static constexpr int K = 12 / V;                              // chunks per spinor
+};
+
+__device__ __forceinline__ cx<float> h2f(unsigned u, float sc) {
+    __half2 h;
+    __builtin_memcpy(&h, &u, 4);
+    const float2 t = __half22float2(h);
+    return {t.x * sc, t.y * sc};
+}
+__device__ __forceinline__ unsigned f2h(float re, float im) {
+    const __half2 h = __floats2half2_rn(re, im);
+    unsigned u;
+    __builtin_memcpy(&u, &h, 4);
+    return u;
+}
+
+// Entry (base + s) with base = site*ls.  Callers with a compile-time Ls pass
+// it as `ls` so the index arithmetic folds.
+template <class S>
+__device__ __forceinline__ void load_spinor_at(CField<S> f, long base, int s, int ls,
+                                               cx<typename S::real> (&v)[12]) {
+    const long q = base * Chunk<S>::K + s;
+    if constexpr (S::has_scale) {
+        const float sc = f.scale[base + s];
+        const nt_u4* p = reinterpret_cast<const nt_u4*>(f.data) + q;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const nt_u4 t = p[(long)k * ls];
+            v[4 * k + 0] = h2f(t.x, sc);
+            v[4 * k + 1] = h2f(t.y, sc);
+            v[4 * k + 2] = h2f(t.z, sc);
+            v[4 * k + 3] = h2f(t.w, sc);
+        }
+    } else if constexpr (sizeof(typename S::real) == 8) {
+        const nt_d2* p = reinterpret_cast<const nt_d2*>(f.data) + q;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const nt_d2 t = p[(long)c * ls];
+            v[c] = {t.x, t.y};
+        }
+    } else {
+        const nt_f4* p = reinterpret_cast<const nt_f4*>(f.data) + q;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const nt_f4 t = p[(long)k * ls];
+            v[2 * k] = {t.x, t.y};
+            v[2 * k + 1] = {t.z, t.w};
+        }
+    }
+}
+
+// entry i -> (base = site*ls, s); 32-bit division whenever the index fits
+__device__ __forceinline__ int entry_lane(long i, int ls) {
+    if (i <= 0xffffffffL) return (int)((unsigned)i % (unsigned)ls);
+    return (int)(i % ls);
 }
 
 template <class S>
 __device__ __forceinline__ void load_spinor(CField<S> f, long i, cx<typename S::real> (&v)[12]) {
-    if constexpr (S::has_scale) {
-        const float sc = f.scale[i];
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            const float2 t = __half22float2(f.data[c * f.N + i]);
-            v[c] = {t.x * sc, t.y * sc};
-        }
-    } else {
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            const auto t = f.data[c * f.N + i];
-            v[c] = {t.x, t.y};
-        }
-    }
+    const int s = entry_lane(i, f.ls);
+    load_spinor_at<S>(f, i - s, s, f.ls, v);
+}
+
+template <class V, bool NT>
+__device__ __forceinline__ void put16(V* p, V v) {
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
 }
 
 // Single-use streams (hop outputs, links) bypass L2 allocation with
 // nontemporal accesses so that the L2 keeps the neighbour spinors, which are
 // re-read by up to eight output sites.
-typedef double nt_d2 __attribute__((ext_vector_type(2)));
-typedef float nt_f2 __attribute__((ext_vector_type(2)));
-
-template <class S>
-__device__ __forceinline__ void store_elem_nt(typename S::elem* p, typename S::real re,
-                                              typename S::real im) {
-    if constexpr (S::has_scale) {
-        const __half2 h = __floats2half2_rn(re, im);
-        __builtin_nontemporal_store(*reinterpret_cast<const unsigned*>(&h),
-                                    reinterpret_cast<unsigned*>(p));
-    } else if constexpr (sizeof(typename S::real) == 8) {
-        nt_d2 t = {re, im};
-        __builtin_nontemporal_store(t, reinterpret_cast<nt_d2*>(p));
-    } else {
-        nt_f2 t = {re, im};
-        __builtin_nontemporal_store(t, reinterpret_cast<nt_f2*>(p));
-    }
-}
-
 template <class S, bool NT = false>
-__device__ __forceinline__ void store_spinor(Field<S> f, long i, const cx<typename S::real> (&v)[12]) {
+__device__ __forceinline__ void store_spinor_at(Field<S> f, long base, int s, int ls,
+                                                const cx<typename S::real> (&v)[12]) {
+    const long q = base * Chunk<S>::K + s;
     if constexpr (S::has_scale) {
         float m = 0.f;
 #pragma unroll
         for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
         const float inv = m > 0.f ? 1.0f / m : 0.f;
         if (NT)
-            __builtin_nontemporal_store(m, f.scale + i);
+            __builtin_nontemporal_store(m, f.scale + base + s);
         else
-            f.scale[i] = m;
+            f.scale[base + s] = m;
+        nt_u4* p = reinterpret_cast<nt_u4*>(f.data) + q;
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            if (NT)
-                store_elem_nt<S>(f.data + c * f.N + i, v[c].re * inv, v[c].im * inv);
-            else
-                f.data[c * f.N + i] = __floats2half2_rn(v[c].re * inv, v[c].im * inv);
+        for (int k = 0; k < 3; ++k) {
+            nt_u4 t;
+            t.x = f2h(v[4 * k + 0].re * inv, v[4 * k + 0].im * inv);
+            t.y = f2h(v[4 * k + 1].re * inv, v[4 * k + 1].im * inv);
+            t.z = f2h(v[4 * k + 2].re * inv, v[4 * k + 2].im * inv);
+            t.w = f2h(v[4 * k + 3].re * inv, v[4 * k + 3].im * inv);
+            put16<nt_u4, NT>(p + (long)k * ls, t);
         }
+    } else if constexpr (sizeof(typename S::real) == 8) {
+        nt_d2* p = reinterpret_cast<nt_d2*>(f.data) + q;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) put16<nt_d2, NT>(p + (long)c * ls, nt_d2{v[c].re, v[c].im});
     } else {
+        nt_f4* p = reinterpret_cast<nt_f4*>(f.data) + q;
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            if (NT) {
-                store_elem_nt<S>(f.data + c * f.N + i, v[c].re, v[c].im);
-            } else {
-                typename S::elem t;
-                t.x = v[c].re;
-                t.y = v[c].im;
-                f.data[c * f.N + i] = t;
-            }
-        }
+        for (int k = 0; k < 6; ++k)
+            put16<nt_f4, NT>(p + (long)k * ls,
+                             nt_f4{v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im});
     }
+}
+
+template <class S, bool NT = false>
+__device__ __forceinline__ void store_spinor(Field<S> f, long i, const cx<typename S::real> (&v)[12]) {
+    const int s = entry_lane(i, f.ls);
+    store_spinor_at<S, NT>(f, i - s, s, f.ls, v);
 }
 
 template <class S, bool NT = false>

@@ -62,7 +62,7 @@ __device__ __forceinline__ void proj_full(int mu, const cx<double> (&p)[12], cx<
 struct ForceArgs {
     CField<F64> a[2];  // by parity
     CField<F64> b[2];
-    const double2* links;  // whole-lattice [par][8][9][Vh], forward dirs 0..3
+    const double2* links;  // whole-lattice [par][Vh][8][9], forward dirs 0..3
     int L[4];
     int Ls;
     long Vh;
@@ -115,7 +115,7 @@ __global__ void force_kernel(ForceArgs a) {
     // eta U_mu(x): forward link of this site (sign folded in)
     cx<double> U[9];
     for (int k = 0; k < 9; ++k) {
-        const double2 t = a.links[((long)(par * 8 + mu) * 9 + k) * a.Vh + cb];
+        const double2 t = a.links[(((long)par * a.Vh + cb) * 8 + mu) * 9 + k];
         U[k] = {t.x, t.y};
     }
     const long lex = (((long)c[3] * a.L[2] + c[2]) * a.L[1] + c[1]) * a.L[0] + c[0];

@@ -18,13 +18,9 @@
 
 // Build-time variants (measured; the defaults are the fastest on gfx950):
 //   MSPCG_HOP_MINWAVES  occupancy hint of __launch_bounds__
-//   MSPCG_HOP_GROUP     directions whose loads are issued before any is used
 //   MSPCG_HOP_NT        nontemporal link loads and output stores
 #ifndef MSPCG_HOP_MINWAVES
 #define MSPCG_HOP_MINWAVES 1
-#endif
-#ifndef MSPCG_HOP_GROUP
-#define MSPCG_HOP_GROUP 1
 #endif
 #ifndef MSPCG_HOP_NT
 #define MSPCG_HOP_NT true
@@ -88,38 +84,32 @@ __device__ __forceinline__ void reconstruct(const cx<T> (&w)[6], cx<T> (&acc)[12
     }
 }
 
-// Direction D = 0..7: mu = D/2, forward (x+mu) for even D, backward for odd D.
-// Loads of a group of directions are issued together before any of them is
-// used, so a thread keeps several neighbour spinors in flight at once.
 template <class S>
-struct DirData {
-    cx<typename S::real> p[12];
-    cx<typename S::real> u[9];
-    bool ok;
-};
-
-template <class S>
-__device__ __forceinline__ void dir_fetch(const HopArgs<S>& a, long nbr, const typename S::elem* lk,
-                                          long lstride, DirData<S>& dd) {
-    load_spinor<S>(a.in, nbr, dd.p);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) dd.u[k] = load_link<S, MSPCG_HOP_NT>(lk + k * lstride);
+__device__ __forceinline__ cx<typename S::real> elem_cx(typename S::elem e) {
+    if constexpr (S::has_scale) {
+        const float2 t = __half22float2(e);
+        return {t.x, t.y};
+    } else {
+        return {e.x, e.y};
+    }
 }
 
-// acc += (1 + SIG g_mu) U in(nbr)
+// acc += (1 + SIG g_mu) U p   (u: the 3x3 link, row-major)
 template <class S, int MU, int SIG>
-__device__ __forceinline__ void dir_apply(const DirData<S>& dd, cx<typename S::real> (&acc)[12]) {
+__device__ __forceinline__ void dir_apply(const cx<typename S::real> (&p)[12],
+                                          const cx<typename S::real> (&u)[9],
+                                          cx<typename S::real> (&acc)[12]) {
     using T = typename S::real;
     cx<T> h[6];
-    project<MU, SIG>(dd.p, h);
+    project<MU, SIG>(p, h);
     cx<T> w[6];
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            cx<T> t = cmul(dd.u[i * 3 + 0], h[sp * 3 + 0]);
-            cfma(t, dd.u[i * 3 + 1], h[sp * 3 + 1]);
-            cfma(t, dd.u[i * 3 + 2], h[sp * 3 + 2]);
+            cx<T> t = cmul(u[i * 3 + 0], h[sp * 3 + 0]);
+            cfma(t, u[i * 3 + 1], h[sp * 3 + 1]);
+            cfma(t, u[i * 3 + 2], h[sp * 3 + 2]);
             w[sp * 3 + i] = t;
         }
     reconstruct<MU, SIG>(w, acc);
@@ -186,14 +176,25 @@ __device__ __forceinline__ void sfor(F&& f) {
     sfor_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-// EPI: the epilogue mixes s (needs the LDS exchange); without it no LDS is
-// allocated, which keeps the occupancy of the plain hop high.
+// EPI: the epilogue mixes s (needs the LDS exchange).  The links of the
+// workgroup's sites are staged in LDS with coalesced 16-byte loads (one load
+// per 16 bytes of links instead of one per element and lane) when they fit;
+// the epilogue reuses that LDS after the direction loop.
 template <class S, int LS, bool DAG, bool EPI>
 __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S> a) {
     using T = typename S::real;
+    using E = typename S::elem;
     constexpr int SPB = 256 / LS;
     constexpr int SITE_STRIDE = LS * 12 + 1;  // LDS row padding against bank conflicts
-    __shared__ cx<T> lds[EPI ? SPB * SITE_STRIDE : 1];
+    constexpr int NCH = 72 * (int)sizeof(E) / 16;  // 16-byte chunks of one site's links
+    constexpr int LSTR = NCH + 1;                  // padded site stride (chunks)
+    constexpr bool LDSL = SPB * LSTR * 16 <= 40 * 1024;
+    constexpr int EPI_BYTES = EPI ? SPB * SITE_STRIDE * (int)sizeof(cx<T>) : 16;
+    constexpr int LNK_BYTES = LDSL ? SPB * LSTR * 16 : 16;
+    constexpr int LDS_BYTES = EPI_BYTES > LNK_BYTES ? EPI_BYTES : LNK_BYTES;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[LDS_BYTES];
+    cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
+    nt_u4* lnk = reinterpret_cast<nt_u4*>(smem);
 
     if (a.done && *a.done) return;
     int bx, d;
@@ -205,10 +206,8 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
     const HopGeom& g = a.g;
     long cb = t_lin;
 
-    cx<T> acc[12];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
     int gc[4] = {0, 0, 0, 0};
+    const E* gl = nullptr;
     if (active) {
         int oc[4];
         if (a.tile[0]) {
@@ -240,40 +239,52 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
         int lc[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) lc[m] = gc[m] - g.link.off[m];
-        const long lcb = box_cb(g.link, lc);
-        const long lstride = g.link.Vh;
-        const typename S::elem* lbase =
-            a.links + (long)d * a.link_dom_stride + (long)g.out_par * 8 * 9 * lstride + lcb;
+        gl = a.links + (long)d * a.link_dom_stride +
+             ((long)g.out_par * g.link.Vh + box_cb(g.link, lc)) * 72;
+        if constexpr (LDSL) {
+            const nt_u4* src = reinterpret_cast<const nt_u4*>(gl);
+            for (int j = s; j < NCH; j += LS) {
+                if constexpr (MSPCG_HOP_NT)
+                    lnk[sl * LSTR + j] = __builtin_nontemporal_load(src + j);
+                else
+                    lnk[sl * LSTR + j] = src[j];
+            }
+        }
+    }
+    if constexpr (LDSL) __syncthreads();
+
+    cx<T> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
+    if (active) {
         const long ibase = (long)d * g.in.Vh;
         // forward terms use (1 - g) and backward (1 + g); the dagger swaps them
         constexpr int SF = DAG ? 1 : -1;
         constexpr int SB = -SF;
-        // directions in groups of MSPCG_HOP_GROUP: fetch all, then apply all
-        constexpr int GRP = MSPCG_HOP_GROUP;
-        static_assert(8 % GRP == 0, "group must divide 8");
-        sfor<8 / GRP>([&](auto gi) {
-            constexpr int G0 = decltype(gi)::value * GRP;
-            DirData<S> dd[GRP];
-            sfor<GRP>([&](auto j) {
-                constexpr int D = G0 + decltype(j)::value;
-                constexpr int MU = D / 2;
-                constexpr bool FWD = (D % 2) == 0;
-                long n = 0;
-                dd[j].ok = neighbour<MU, FWD ? 1 : 0>(g, gc, n);
-                if (dd[j].ok)
-                    dir_fetch<S>(a, (ibase + n) * LS + s, lbase + (FWD ? MU : 4 + MU) * 9 * lstride,
-                                 lstride, dd[j]);
-            });
-            sfor<GRP>([&](auto j) {
-                constexpr int D = G0 + decltype(j)::value;
-                constexpr int MU = D / 2;
-                constexpr bool FWD = (D % 2) == 0;
-                if (dd[j].ok) dir_apply<S, MU, FWD ? SF : SB>(dd[j], acc);
-            });
+        sfor<8>([&](auto di) {
+            constexpr int D = decltype(di)::value;
+            constexpr int MU = D / 2;
+            constexpr bool FWD = (D % 2) == 0;
+            constexpr int LD = (FWD ? MU : 4 + MU) * 9;  // first entry of this link
+            long n = 0;
+            if (neighbour<MU, FWD ? 1 : 0>(g, gc, n)) {
+                cx<T> p[12];
+                load_spinor_at<S>(a.in, (ibase + n) * LS, s, LS, p);
+                cx<T> u[9];
+                if constexpr (LDSL) {
+                    const E* le = reinterpret_cast<const E*>(lnk + sl * LSTR) + LD;
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) u[k] = elem_cx<S>(le[k]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) u[k] = load_link<S, MSPCG_HOP_NT>(gl + LD + k);
+                }
+                dir_apply<S, MU, FWD ? SF : SB>(p, u, acc);
+            }
         });
     }
 
-    const long oidx = ((long)d * g.out.Vh + cb) * LS + s;
+    const long obase = ((long)d * g.out.Vh + cb) * LS;
     cx<T> res[12];
     const T mf = (T)a.mf;
     if (!EPI || a.ph.identity) {
@@ -283,6 +294,7 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
             res[c] = {acc[c].re * sc, acc[c].im * sc};
         }
     } else {
+        if constexpr (LDSL) __syncthreads();  // every wave is done with the staged links
         if (active) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) lds[sl * SITE_STRIDE + s * 12 + c] = acc[c];
@@ -315,7 +327,7 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
                 ac[m] = gc[m] - g.aux.off[m];
                 in = in && ac[m] >= 0 && ac[m] < g.aux.E[m];
             }
-            if (in) load_spinor<S>(a.aux, ((long)d * g.aux.Vh + box_cb(g.aux, ac)) * LS + s, x);
+            if (in) load_spinor_at<S>(a.aux, ((long)d * g.aux.Vh + box_cb(g.aux, ac)) * LS, s, LS, x);
         }
         if (!EPI || a.pa.identity) {
 #pragma unroll
@@ -350,7 +362,7 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
         }
     }
 
-    if (active) store_spinor<S, MSPCG_HOP_NT>(a.out, oidx, res);
+    if (active) store_spinor_at<S, MSPCG_HOP_NT>(a.out, obase, s, LS, res);
     if (a.partials) {
         double n2 = 0;
         if (active) {

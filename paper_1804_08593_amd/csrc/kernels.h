@@ -130,7 +130,7 @@ int launch_axpy(double2* y, const double2* x, double a, long N, hipStream_t st);
 int launch_cg_update_xr32(float2* x, float2* r, const float2* p, const float2* q, long N,
                           const DevScalars* sc, double* partials, long nparts, hipStream_t st);
 int launch_xpay32(float2* p, const float2* r, long N, const DevScalars* sc, hipStream_t st);
-int launch_accum32(double2* x, float2* xs, long N, hipStream_t st);
+int launch_accum32(double2* x, float2* xs, long N, int Ls, hipStream_t st);
 
 // Mixed-precision conversions (whole vectors)
 template <class SI, class SO>

@@ -142,12 +142,12 @@ __global__ void pack_links_kernel(const double2* U, typename S::elem* out, DomGr
                                   int antiperiodic_t, long V4) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const int d = blockIdx.y;
-    const long per_par = lb.Vh * 8;
-    if (i >= 2 * per_par) return;
-    const int par = (int)(i / per_par);
-    const long rem = i - par * per_par;
-    const int dir = (int)(rem / lb.Vh);
-    const long cb = rem - (long)dir * lb.Vh;
+    // consecutive threads take the 8 directions of one site (contiguous output)
+    if (i >= 2 * 8 * lb.Vh) return;
+    const long ps = i >> 3;
+    const int dir = (int)(i & 7);
+    const int par = (int)(ps / lb.Vh);
+    const long cb = ps - par * lb.Vh;
     int c[4];
     box_coords(lb, cb, par, c);
     int dc[4];
@@ -175,7 +175,7 @@ __global__ void pack_links_kernel(const double2* U, typename S::elem* out, DomGr
         sign = -1.0;
     }
     const double2* u = U + ((long)mu * V4 + lex_of(y, g.L)) * 9;
-    const long obase = (long)d * (2 * 8 * 9 * lb.Vh) + ((long)(par * 8 + dir) * 9) * lb.Vh + cb;
+    const long obase = (long)d * (2 * 72 * lb.Vh) + ((long)par * lb.Vh + cb) * 72 + dir * 9;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const int row = k / 3, col = k % 3;
@@ -194,7 +194,7 @@ __global__ void pack_links_kernel(const double2* U, typename S::elem* out, DomGr
             e.x = (typename S::real)v.x;
             e.y = (typename S::real)v.y;
         }
-        out[obase + (long)k * lb.Vh] = e;
+        out[obase + k] = e;
     }
 }
 

@@ -132,16 +132,16 @@ __global__ void inner_start_kernel(CField<F64> r, Field<S> rho, Field<S> p, DomG
         }
         const long gcb = ((((long)gc[3] * g.L[2] + gc[2]) * g.L[1] + gc[1]) * g.L[0] + gc[0]) >> 1;
         cx<double> v[12];
-        load_spinor<F64>(r, gcb * Ls + s, v);
+        load_spinor_at<F64>(r, gcb * Ls, s, Ls, v);
         cx<typename S::real> w[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             w[k] = {(typename S::real)v[k].re, (typename S::real)v[k].im};
             n2 += (double)w[k].re * w[k].re + (double)w[k].im * w[k].im;
         }
-        const long i = ((long)d * Vhb + cb) * Ls + s;
-        store_spinor<S>(rho, i, w);
-        store_spinor<S>(p, i, w);
+        const long ib = ((long)d * Vhb + cb) * Ls;
+        store_spinor_at<S>(rho, ib, s, Ls, w);
+        store_spinor_at<S>(p, ib, s, Ls, w);
     }
     block_reduce_store(n2, partials + (long)d * gridDim.x + blockIdx.x);
 }
@@ -158,11 +158,13 @@ __global__ void inner_update_kernel(Field<S> z, Field<S> rho, CField<S> p, CFiel
     if (j < n_dom) {
         const long i = (long)d * n_dom + j;
         const T a = (T)sc.a[d];
+        const int ls = p.ls, s = entry_lane(i, ls);
+        const long ib = i - s;
         cx<T> pv[12], wv[12], zv[12], rv[12];
-        load_spinor<S>(p, i, pv);
-        load_spinor<S>(w, i, wv);
-        load_spinor<S>(cfield(rho), i, rv);
-        if (!first) load_spinor<S>(cfield(z), i, zv);
+        load_spinor_at<S>(p, ib, s, ls, pv);
+        load_spinor_at<S>(w, ib, s, ls, wv);
+        load_spinor_at<S>(cfield(rho), ib, s, ls, rv);
+        if (!first) load_spinor_at<S>(cfield(z), ib, s, ls, zv);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             if (first) zv[k] = {0, 0};
@@ -172,8 +174,8 @@ __global__ void inner_update_kernel(Field<S> z, Field<S> rho, CField<S> p, CFiel
             rv[k].im -= a * wv[k].im;
             n2 += (double)rv[k].re * rv[k].re + (double)rv[k].im * rv[k].im;
         }
-        store_spinor<S>(z, i, zv);
-        store_spinor<S>(rho, i, rv);
+        store_spinor_at<S>(z, ib, s, ls, zv);
+        store_spinor_at<S>(rho, ib, s, ls, rv);
     }
     block_reduce_store(n2, partials + (long)d * gridDim.x + blockIdx.x);
 }
@@ -189,15 +191,17 @@ __global__ void inner_xpay_kernel(Field<S> p, CField<S> rho, long n_dom, InnerSc
     if (j >= n_dom) return;
     const long i = (long)d * n_dom + j;
     const T b = (T)sc.beta[d];
+    const int ls = p.ls, s = entry_lane(i, ls);
+    const long ib = i - s;
     cx<T> pv[12], rv[12];
-    load_spinor<S>(cfield(p), i, pv);
-    load_spinor<S>(rho, i, rv);
+    load_spinor_at<S>(cfield(p), ib, s, ls, pv);
+    load_spinor_at<S>(rho, ib, s, ls, rv);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
         pv[k].re = rv[k].re + b * pv[k].re;
         pv[k].im = rv[k].im + b * pv[k].im;
     }
-    store_spinor<S>(p, i, pv);
+    store_spinor_at<S>(p, ib, s, ls, pv);
 }
 
 int last_error() { return hipGetLastError() == hipSuccess ? 0 : MSPCG_EHIP; }

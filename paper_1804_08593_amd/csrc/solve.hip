@@ -372,7 +372,7 @@ struct MixedSolver : Solver {
         }
         if (s.done || iters >= p->maxiter) {
             // reliable update: x += xs ; r = bhat - A x in FP64 ; rs = r
-            if (launch_accum32(x.data, xs.data, c->Nh, st)) return MSPCG_EHIP;
+            if (launch_accum32(x.data, xs.data, c->Nh, c->Ls, st)) return MSPCG_EHIP;
             if ((e = true_residual(c, r, bhat, cfield(x), st, true_rr))) return e;
             restarts++;
             if (true_rr <= tol2) {
