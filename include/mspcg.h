@@ -152,7 +152,8 @@ enum {
     MSPCG_KC_HOPDOM = 2, /* block-domain hop of the local solves (inner precision) */
     MSPCG_KC_FIVED = 3,  /* 5D-only kernels */
     MSPCG_KC_BLAS = 4,   /* vector updates, reductions, conversions */
-    MSPCG_KC_COUNT = 5
+    MSPCG_KC_HOPCG = 5,  /* last hop of A with the CG vector update fused in (FP64/FP32) */
+    MSPCG_KC_COUNT = 6
 };
 
 typedef struct {

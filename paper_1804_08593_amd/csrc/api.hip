@@ -172,9 +172,9 @@ static int kc_hop() {
 }
 
 template <class S>
-int op_hop(mspcg_ctx* c, Field<S> out, CField<S> in, int out_par, bool dag, const FiveDProg& ph,
-           const CField<S>* aux, const FiveDProg& pa, double* partials, const int* done,
-           hipStream_t st) {
+static int op_hop_ex(mspcg_ctx* c, Field<S> out, CField<S> in, int out_par, bool dag,
+                     const FiveDProg& ph, const CField<S>* aux, const FiveDProg& pa,
+                     double* partials, const int* done, const CgUpdate<S>* cg, hipStream_t st) {
     HopArgs<S> a;
     memset(&a, 0, sizeof(a));
     a.in = in;
@@ -193,16 +193,34 @@ int op_hop(mspcg_ctx* c, Field<S> out, CField<S> in, int out_par, bool dag, cons
     a.done = done;
     a.xcd_remap = c->tune.xcd_remap;
     pick_tile(c->tune.tile[prec_index<S>()], c->lat, a.tile);
-    const double bytes = (double)c->Nh * S::bytes_spinor * (2 + (aux ? 1 : 0)) +
-                         (double)c->Vh * 8 * S::bytes_link;
-    Timed t(c, kc_hop<S>(), bytes, st);
+    // spinor passes: in, out, aux; a fused CG update reads r, x, p and writes
+    // r, x (and out only if it is kept)
+    int passes = 2 + (aux ? 1 : 0);
+    if (cg) {
+        a.cg_r = cg->r;
+        a.cg_x = cg->x;
+        a.cg_p = cg->p;
+        a.cg_sc = cg->sc;
+        a.cg_keep_out = cg->keep_out;
+        passes += 5 - (cg->keep_out ? 0 : 1);
+    }
+    const double bytes = (double)c->Nh * S::bytes_spinor * passes + (double)c->Vh * 8 * S::bytes_link;
+    Timed t(c, cg ? MSPCG_KC_HOPCG : kc_hop<S>(), bytes, st);
     return launch_hop<S>(a, c->Ls, 1, dag, st);
+}
+
+template <class S>
+int op_hop(mspcg_ctx* c, Field<S> out, CField<S> in, int out_par, bool dag, const FiveDProg& ph,
+           const CField<S>* aux, const FiveDProg& pa, double* partials, const int* done,
+           hipStream_t st) {
+    return op_hop_ex<S>(c, out, in, out_par, dag, ph, aux, pa, partials, done, nullptr, st);
 }
 
 template <class S>
 int op_fived(mspcg_ctx* c, Field<S> out, CField<S> in, const FiveDProg& p, double* partials,
              const int* done, hipStream_t st) {
     FiveDArgs<S> a;
+    memset(&a, 0, sizeof(a));
     a.in = in;
     a.out = out;
     a.Vh = c->Vh;
@@ -237,6 +255,61 @@ int op_mhatdag(mspcg_ctx* c, Field<S> q, CField<S> y, const int* done, hipStream
     return op_hop<S>(c, q, cfield(v), 0, true, scaled(c->pr.Bdag, -0.25, -0.25), &y, c->pr.M5dag,
                      nullptr, done, st);
 }
+
+// One CG step around q = A p with the vector updates fused into the operator
+// kernels: p = src + beta p rides on the first 5D kernel (t = B p), alpha =
+// (flexible ? zr : rr) / |Mhat p|^2 is formed after the Mhat half, and the last
+// hop does r -= alpha q, x += alpha p with |r|^2 partials (q stored only when
+// keep_q).  The caller follows with launch_cg_beta over hop_nparts partials.
+template <class S>
+int cg_step(mspcg_ctx* c, Field<S> x, Field<S> r, Field<S> p, Field<S> q, CField<S> src,
+            bool keep_q, bool flexible, const int* done, hipStream_t st) {
+    const std::string pfx = std::is_same<S, F64>::value ? "d." : "s.";
+    Field<S> t = half_field<S>(c, pfx + "mh_t", c->Nh);
+    Field<S> u = half_field<S>(c, pfx + "mh_u", c->Nh);
+    Field<S> y = half_field<S>(c, pfx + "A_y", c->Nh);
+    Field<S> v = half_field<S>(c, pfx + "mh_v", c->Nh);
+    if (!t.data || !u.data || !y.data || !v.data) return MSPCG_ENOMEM;
+    int e;
+    {
+        FiveDArgs<S> a;
+        memset(&a, 0, sizeof(a));
+        a.in = cfield(p);
+        a.out = t;
+        a.Vh = c->Vh;
+        a.p = c->pr.B;
+        a.mf = c->act.mf;
+        a.done = done;
+        a.xp_src = src;
+        a.xp_in = p;
+        a.xp_sc = c->sc;
+        Timed tm(c, MSPCG_KC_FIVED, (double)c->Nh * S::bytes_spinor * 4, st);
+        if (launch_fived<S>(a, c->Ls, 1, st)) return MSPCG_EHIP;
+    }
+    const CField<S> pc = cfield(p);
+    if ((e = op_hop<S>(c, u, cfield(t), 1, false, c->pr.X, nullptr, c->pr.id, nullptr, done, st)))
+        return e;
+    if ((e = op_hop<S>(c, y, cfield(u), 0, false, prog_scale(-0.25), &pc, c->pr.M5, c->partials,
+                       done, st)))
+        return e;
+    if (launch_cg_alpha(c->sc, c->partials, (int)hop_nparts(c), st, flexible ? 1 : 0))
+        return MSPCG_EHIP;
+    if ((e = op_hop<S>(c, v, cfield(y), 1, true, c->pr.Xdag, nullptr, c->pr.id, nullptr, done, st)))
+        return e;
+    CgUpdate<S> cg;
+    cg.r = r;
+    cg.x = x;
+    cg.p = pc;
+    cg.sc = c->sc;
+    cg.keep_out = keep_q ? 1 : 0;
+    const CField<S> yc = cfield(y);
+    return op_hop_ex<S>(c, q, cfield(v), 0, true, scaled(c->pr.Bdag, -0.25, -0.25), &yc,
+                        c->pr.M5dag, c->partials, done, &cg, st);
+}
+template int cg_step<F64>(mspcg_ctx*, Field<F64>, Field<F64>, Field<F64>, Field<F64>, CField<F64>,
+                          bool, bool, const int*, hipStream_t);
+template int cg_step<F32>(mspcg_ctx*, Field<F32>, Field<F32>, Field<F32>, Field<F32>, CField<F32>,
+                          bool, bool, const int*, hipStream_t);
 
 template <class S>
 int op_A(mspcg_ctx* c, Field<S> q, CField<S> p, double* partials, const int* done,

@@ -41,6 +41,18 @@ __global__ __launch_bounds__(256) void fived_kernel(FiveDArgs<S> a) {
     cx<T> v[12];
     if (active) {
         load_spinor_at<S>(a.in, ib, s, LS, v);
+        if (a.xp_src.data) {
+            // search-direction update p = src + beta p, written back in place
+            const T b = (T)a.xp_sc->beta;
+            cx<T> r[12];
+            load_spinor_at<S>(a.xp_src, ib, s, LS, r);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                v[c].re = r[c].re + b * v[c].re;
+                v[c].im = r[c].im + b * v[c].im;
+            }
+            store_spinor_at<S>(a.xp_in, ib, s, LS, v);
+        }
 #pragma unroll
         for (int c = 0; c < 12; ++c) lds[sl * SITE_STRIDE + s * 12 + c] = v[c];
     }

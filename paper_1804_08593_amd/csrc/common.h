@@ -116,39 +116,57 @@ __device__ __forceinline__ unsigned f2h(float re, float im) {
     return u;
 }
 
+// The undecoded 16-byte chunks of one entry (+ its FP16 scale): loading raw
+// chunks first and decoding later lets a thread keep several neighbour
+// spinors in flight in few registers.
+template <class S>
+struct RawSpinor {
+    nt_u4 c[Chunk<S>::K];
+    float sc;
+};
+
 // Entry (base + s) with base = site*ls.  Callers with a compile-time Ls pass
 // it as `ls` so the index arithmetic folds.
 template <class S>
-__device__ __forceinline__ void load_spinor_at(CField<S> f, long base, int s, int ls,
-                                               cx<typename S::real> (&v)[12]) {
-    const long q = base * Chunk<S>::K + s;
+__device__ __forceinline__ void load_raw_at(CField<S> f, long base, int s, int ls, RawSpinor<S>& r) {
+    const nt_u4* p = reinterpret_cast<const nt_u4*>(f.data) + base * Chunk<S>::K + s;
+#pragma unroll
+    for (int k = 0; k < Chunk<S>::K; ++k) r.c[k] = p[(long)k * ls];
+    if constexpr (S::has_scale) r.sc = f.scale[base + s];
+}
+
+template <class S>
+__device__ __forceinline__ void decode_raw(const RawSpinor<S>& r, cx<typename S::real> (&v)[12]) {
     if constexpr (S::has_scale) {
-        const float sc = f.scale[base + s];
-        const nt_u4* p = reinterpret_cast<const nt_u4*>(f.data) + q;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const nt_u4 t = p[(long)k * ls];
-            v[4 * k + 0] = h2f(t.x, sc);
-            v[4 * k + 1] = h2f(t.y, sc);
-            v[4 * k + 2] = h2f(t.z, sc);
-            v[4 * k + 3] = h2f(t.w, sc);
+            v[4 * k + 0] = h2f(r.c[k].x, r.sc);
+            v[4 * k + 1] = h2f(r.c[k].y, r.sc);
+            v[4 * k + 2] = h2f(r.c[k].z, r.sc);
+            v[4 * k + 3] = h2f(r.c[k].w, r.sc);
         }
     } else if constexpr (sizeof(typename S::real) == 8) {
-        const nt_d2* p = reinterpret_cast<const nt_d2*>(f.data) + q;
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            const nt_d2 t = p[(long)c * ls];
+            const nt_d2 t = __builtin_bit_cast(nt_d2, r.c[c]);
             v[c] = {t.x, t.y};
         }
     } else {
-        const nt_f4* p = reinterpret_cast<const nt_f4*>(f.data) + q;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            const nt_f4 t = p[(long)k * ls];
+            const nt_f4 t = __builtin_bit_cast(nt_f4, r.c[k]);
             v[2 * k] = {t.x, t.y};
             v[2 * k + 1] = {t.z, t.w};
         }
     }
+}
+
+template <class S>
+__device__ __forceinline__ void load_spinor_at(CField<S> f, long base, int s, int ls,
+                                               cx<typename S::real> (&v)[12]) {
+    RawSpinor<S> r;
+    load_raw_at<S>(f, base, s, ls, r);
+    decode_raw<S>(r, v);
 }
 
 // entry i -> (base = site*ls, s); 32-bit division whenever the index fits

@@ -131,6 +131,17 @@ int op_mhatdag(mspcg_ctx* c, Field<S> q, CField<S> y, const int* done, hipStream
 template <class S>
 int op_A(mspcg_ctx* c, Field<S> q, CField<S> p, double* partials, const int* done,
          hipStream_t st);
+// fused CG update of a whole-lattice hop (see HopArgs)
+template <class S>
+struct CgUpdate {
+    Field<S> r, x;
+    CField<S> p;
+    const DevScalars* sc;
+    int keep_out;
+};
+template <class S>
+int cg_step(mspcg_ctx* c, Field<S> x, Field<S> r, Field<S> p, Field<S> q, CField<S> src,
+            bool keep_q, bool flexible, const int* done, hipStream_t st);
 long hop_nparts(mspcg_ctx* c);
 // traversal tile for a box: the largest even divisor of each extent that does
 // not exceed the preferred tile (all zero: lexicographic order)

@@ -10,6 +10,7 @@
 // (1 + sig g_mu) psi = [h ; sig e_mu^+ h] with h = psi_up + sig e_mu psi_dn,
 // so only the 2x3 half spinor h is multiplied by the link.
 //   e_x = -i sigma_x, e_y = -i sigma_y, e_z = -i sigma_z, e_t = 1.
+#pragma once
 #include <utility>
 
 #include "common.h"
@@ -19,11 +20,23 @@
 // Build-time variants (measured; the defaults are the fastest on gfx950):
 //   MSPCG_HOP_MINWAVES  occupancy hint of __launch_bounds__
 //   MSPCG_HOP_NT        nontemporal link loads and output stores
+//   MSPCG_HOP_PF*       neighbour loads kept in flight per thread
 #ifndef MSPCG_HOP_MINWAVES
 #define MSPCG_HOP_MINWAVES 1
 #endif
 #ifndef MSPCG_HOP_NT
 #define MSPCG_HOP_NT true
+#endif
+// MSPCG_HOP_PF{64,32,16}: directions whose raw neighbour spinors are loaded
+// before any of them is decoded and applied (per storage precision)
+#ifndef MSPCG_HOP_PF64
+#define MSPCG_HOP_PF64 1
+#endif
+#ifndef MSPCG_HOP_PF32
+#define MSPCG_HOP_PF32 1
+#endif
+#ifndef MSPCG_HOP_PF16
+#define MSPCG_HOP_PF16 1
 #endif
 
 namespace mspcg {
@@ -176,11 +189,12 @@ __device__ __forceinline__ void sfor(F&& f) {
     sfor_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-// EPI: the epilogue mixes s (needs the LDS exchange).  The links of the
+// EPH / EPA: the hop-output / aux program mixes s (needs the LDS exchange;
+// separate flags keep the register footprint of the common cases low).  The links of the
 // workgroup's sites are staged in LDS with coalesced 16-byte loads (one load
 // per 16 bytes of links instead of one per element and lane) when they fit;
 // the epilogue reuses that LDS after the direction loop.
-template <class S, int LS, bool DAG, bool EPI>
+template <class S, int LS, bool DAG, bool EPH, bool EPA, bool CG = false>
 __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S> a) {
     using T = typename S::real;
     using E = typename S::elem;
@@ -189,6 +203,7 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
     constexpr int NCH = 72 * (int)sizeof(E) / 16;  // 16-byte chunks of one site's links
     constexpr int LSTR = NCH + 1;                  // padded site stride (chunks)
     constexpr bool LDSL = SPB * LSTR * 16 <= 40 * 1024;
+    constexpr bool EPI = EPH || EPA;
     constexpr int EPI_BYTES = EPI ? SPB * SITE_STRIDE * (int)sizeof(cx<T>) : 16;
     constexpr int LNK_BYTES = LDSL ? SPB * LSTR * 16 : 16;
     constexpr int LDS_BYTES = EPI_BYTES > LNK_BYTES ? EPI_BYTES : LNK_BYTES;
@@ -261,33 +276,49 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
         // forward terms use (1 - g) and backward (1 + g); the dagger swaps them
         constexpr int SF = DAG ? 1 : -1;
         constexpr int SB = -SF;
-        sfor<8>([&](auto di) {
-            constexpr int D = decltype(di)::value;
-            constexpr int MU = D / 2;
-            constexpr bool FWD = (D % 2) == 0;
-            constexpr int LD = (FWD ? MU : 4 + MU) * 9;  // first entry of this link
-            long n = 0;
-            if (neighbour<MU, FWD ? 1 : 0>(g, gc, n)) {
-                cx<T> p[12];
-                load_spinor_at<S>(a.in, (ibase + n) * LS, s, LS, p);
-                cx<T> u[9];
-                if constexpr (LDSL) {
-                    const E* le = reinterpret_cast<const E*>(lnk + sl * LSTR) + LD;
+        constexpr int PF = S::has_scale ? MSPCG_HOP_PF16
+                           : sizeof(T) == 8  ? MSPCG_HOP_PF64
+                                             : MSPCG_HOP_PF32;
+        static_assert(8 % PF == 0, "prefetch group must divide 8");
+        sfor<8 / PF>([&](auto gi) {
+            constexpr int G0 = decltype(gi)::value * PF;
+            RawSpinor<S> raw[PF];
+            bool ok[PF];
+            sfor<PF>([&](auto j) {
+                constexpr int D = G0 + decltype(j)::value;
+                constexpr int MU = D / 2;
+                constexpr bool FWD = (D % 2) == 0;
+                long n = 0;
+                ok[j] = neighbour<MU, FWD ? 1 : 0>(g, gc, n);
+                if (ok[j]) load_raw_at<S>(a.in, (ibase + n) * LS, s, LS, raw[j]);
+            });
+            sfor<PF>([&](auto j) {
+                constexpr int D = G0 + decltype(j)::value;
+                constexpr int MU = D / 2;
+                constexpr bool FWD = (D % 2) == 0;
+                constexpr int LD = (FWD ? MU : 4 + MU) * 9;  // first entry of this link
+                if (ok[j]) {
+                    cx<T> p[12];
+                    decode_raw<S>(raw[j], p);
+                    cx<T> u[9];
+                    if constexpr (LDSL) {
+                        const E* le = reinterpret_cast<const E*>(lnk + sl * LSTR) + LD;
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) u[k] = elem_cx<S>(le[k]);
-                } else {
+                        for (int k = 0; k < 9; ++k) u[k] = elem_cx<S>(le[k]);
+                    } else {
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) u[k] = load_link<S, MSPCG_HOP_NT>(gl + LD + k);
+                        for (int k = 0; k < 9; ++k) u[k] = load_link<S, MSPCG_HOP_NT>(gl + LD + k);
+                    }
+                    dir_apply<S, MU, FWD ? SF : SB>(p, u, acc);
                 }
-                dir_apply<S, MU, FWD ? SF : SB>(p, u, acc);
-            }
+            });
         });
     }
 
     const long obase = ((long)d * g.out.Vh + cb) * LS;
     cx<T> res[12];
     const T mf = (T)a.mf;
-    if (!EPI || a.ph.identity) {
+    if (!EPH || a.ph.identity) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
             const T sc = (T)(c < 6 ? a.ph.scale[0] : a.ph.scale[1]);
@@ -329,7 +360,7 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
             }
             if (in) load_spinor_at<S>(a.aux, ((long)d * g.aux.Vh + box_cb(g.aux, ac)) * LS, s, LS, x);
         }
-        if (!EPI || a.pa.identity) {
+        if (!EPA || a.pa.identity) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 const T sc = (T)(c < 6 ? a.pa.scale[0] : a.pa.scale[1]);
@@ -362,6 +393,34 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
         }
     }
 
+    if constexpr (CG) {
+        // fused CG update: r -= alpha out, x += alpha p, partials of |r|^2
+        double n2 = 0;
+        if (active) {
+            if (a.cg_keep_out) store_spinor_at<S, MSPCG_HOP_NT>(a.out, obase, s, LS, res);
+            const T al = (T)a.cg_sc->alpha;
+            cx<T> v[12];
+            load_spinor_at<S>(cfield(a.cg_r), obase, s, LS, v);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                v[c].re -= al * res[c].re;
+                v[c].im -= al * res[c].im;
+                n2 += (double)v[c].re * v[c].re + (double)v[c].im * v[c].im;
+            }
+            store_spinor_at<S>(a.cg_r, obase, s, LS, v);
+            cx<T> pv[12];
+            load_spinor_at<S>(a.cg_p, obase, s, LS, pv);
+            load_spinor_at<S>(cfield(a.cg_x), obase, s, LS, v);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                v[c].re += al * pv[c].re;
+                v[c].im += al * pv[c].im;
+            }
+            store_spinor_at<S>(a.cg_x, obase, s, LS, v);
+        }
+        block_sum_store<S, LS>(n2, a.partials + (long)d * gridDim.x + bx);
+        return;
+    }
     if (active) store_spinor_at<S, MSPCG_HOP_NT>(a.out, obase, s, LS, res);
     if (a.partials) {
         double n2 = 0;
@@ -380,22 +439,38 @@ static void launch_ls(const HopArgs<S>& a, int ndom, bool dag, hipStream_t st) {
     constexpr int SPB = 256 / LS;
     dim3 grid((unsigned)((a.g.out.Vh + SPB - 1) / SPB), (unsigned)ndom);
     dim3 block(SPB * LS);
-    const bool epi = !a.ph.identity || (a.has_aux && !a.pa.identity);
-    if (dag) {
-        if (epi)
-            hipLaunchKernelGGL((hop_kernel<S, LS, true, true>), grid, block, 0, st, a);
-        else
-            hipLaunchKernelGGL((hop_kernel<S, LS, true, false>), grid, block, 0, st, a);
-    } else {
-        if (epi)
-            hipLaunchKernelGGL((hop_kernel<S, LS, false, true>), grid, block, 0, st, a);
-        else
-            hipLaunchKernelGGL((hop_kernel<S, LS, false, false>), grid, block, 0, st, a);
+    const bool eph = !a.ph.identity;
+    const bool epa = a.has_aux && !a.pa.identity;
+    if (a.cg_r.data) {
+        // the fused CG update only follows the last (dagger) hop of A in FP64
+        // and FP32; the epilogue variant also handles identity programs
+        if constexpr (S::has_scale) {
+            return;
+        } else {
+            if (dag)
+                hipLaunchKernelGGL((hop_kernel<S, LS, true, true, true, true>), grid, block, 0, st, a);
+            return;
+        }
     }
+#define MSPCG_HOP_LAUNCH(D, H, A) \
+    hipLaunchKernelGGL((hop_kernel<S, LS, D, H, A>), grid, block, 0, st, a)
+    if (dag) {
+        if (eph && epa) MSPCG_HOP_LAUNCH(true, true, true);
+        else if (eph) MSPCG_HOP_LAUNCH(true, true, false);
+        else if (epa) MSPCG_HOP_LAUNCH(true, false, true);
+        else MSPCG_HOP_LAUNCH(true, false, false);
+    } else {
+        if (eph && epa) MSPCG_HOP_LAUNCH(false, true, true);
+        else if (eph) MSPCG_HOP_LAUNCH(false, true, false);
+        else if (epa) MSPCG_HOP_LAUNCH(false, false, true);
+        else MSPCG_HOP_LAUNCH(false, false, false);
+    }
+#undef MSPCG_HOP_LAUNCH
 }
 
 template <class S>
 int launch_hop(const HopArgs<S>& a, int Ls, int ndom, bool dag, hipStream_t st) {
+    if (a.cg_r.data && (S::has_scale || !dag || ndom != 1)) return -1;
     switch (Ls) {
 #define MSPCG_CASE(L) \
     case L: launch_ls<S, L>(a, ndom, dag, st); break;
@@ -411,12 +486,5 @@ long hop_grid_x(long Vh, int Ls) {
     const int spb = 256 / Ls;
     return (Vh + spb - 1) / spb;
 }
-
-template int launch_hop<F64>(const HopArgs<F64>&, int, int, bool, hipStream_t);
-template int launch_hop<F32>(const HopArgs<F32>&, int, int, bool, hipStream_t);
-template int launch_hop<F16>(const HopArgs<F16>&, int, int, bool, hipStream_t);
-template long hop_grid_x<F64>(long, int);
-template long hop_grid_x<F32>(long, int);
-template long hop_grid_x<F16>(long, int);
 
 }  // namespace mspcg

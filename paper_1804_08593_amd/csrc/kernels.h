@@ -17,6 +17,8 @@ struct HopGeom {
                    // box spans the lattice there); clear: drop hops leaving the box
 };
 
+struct DevScalars;
+
 template <class S>
 struct HopArgs {
     CField<S> in;
@@ -33,6 +35,14 @@ struct HopArgs {
     const int* done;   // optional: skip the launch when *done != 0
     int xcd_remap;     // map workgroups so each XCD walks a contiguous site range
     int tile[4];       // nonzero: traverse output sites in 4D tiles of this extent
+    // optional CG update fused after the output is formed (whole-lattice hops):
+    //   r -= alpha out ; x += alpha p ; partials = |r|^2 ; out is stored only
+    //   when cg_keep_out.  alpha is read from cg_sc.
+    Field<S> cg_r;
+    Field<S> cg_x;
+    CField<S> cg_p;
+    const DevScalars* cg_sc;
+    int cg_keep_out;
 };
 
 template <class S>
@@ -50,6 +60,11 @@ struct FiveDArgs {
     double mf;
     double* partials;
     const int* done;
+    // optional search-direction update before the program: in = src + beta in,
+    // written back through xp_in (the same field as `in`); beta from xp_sc
+    CField<S> xp_src;
+    Field<S> xp_in;
+    const DevScalars* xp_sc;
 };
 template <class S>
 int launch_fived(const FiveDArgs<S>& a, int Ls, int ndom, hipStream_t st);

@@ -320,6 +320,7 @@ template <class S>
 static int dom_fived(mspcg_ctx* c, Field<S> out, CField<S> in, long Vh, const FiveDProg& p,
                      const int* done, hipStream_t st) {
     FiveDArgs<S> a;
+    memset(&a, 0, sizeof(a));
     a.in = in;
     a.out = out;
     a.Vh = Vh;

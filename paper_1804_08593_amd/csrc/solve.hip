@@ -162,15 +162,12 @@ struct CGSolver : Solver {
         true_rr = rr;
         return push(c, st, s);
     }
+    // p = r + beta p ; q = A p ; x += alpha p ; r -= alpha q ; beta  (all fused
+    // into the operator kernels; beta = 0 on the first step makes p = r)
     int iterate(hipStream_t st) override {
         int e;
-        if ((e = op_A<F64>(c, q, cfield(pp), c->partials, &c->sc->done, st))) return e;
-        if (launch_cg_alpha(c->sc, c->partials, (int)nph, st)) return MSPCG_EHIP;
-        if (launch_cg_update_xr(x.data, r.data, pp.data, q.data, c->Nh, c->sc, c->partials, npb,
-                                st))
-            return MSPCG_EHIP;
-        if (launch_cg_beta(c->sc, c->partials, (int)npb, c->hist, cap, st)) return MSPCG_EHIP;
-        if (launch_xpay(pp.data, r.data, c->Nh, c->sc, 0, st)) return MSPCG_EHIP;
+        if ((e = cg_step<F64>(c, x, r, pp, q, cfield(r), false, false, &c->sc->done, st))) return e;
+        if (launch_cg_beta(c->sc, c->partials, (int)nph, c->hist, cap, st)) return MSPCG_EHIP;
         return 0;
     }
     int after_poll(hipStream_t st) override {
@@ -186,14 +183,13 @@ struct CGSolver : Solver {
                 converged = finished = true;
                 return 0;
             }
-            // continue from the true residual: the step that set `done` skipped
-            // p = r + beta p, so redo it with beta = |r_true|^2 / |r_prev|^2
+            // continue from the true residual: the next step forms p = r + beta p
+            // with beta = |r_true|^2 / |r_prev|^2
             restarts++;
             s.beta = s.beta * true_rr / s.rr;
             s.rr = true_rr;
             s.done = 0;
             if ((e = push(c, st, s))) return e;
-            if (launch_xpay(pp.data, r.data, c->Nh, c->sc, 0, st)) return MSPCG_EHIP;
         }
         if (iters >= p->maxiter) {
             if ((e = true_residual(c, r, bhat, cfield(x), st, true_rr))) return e;
@@ -217,7 +213,6 @@ struct MSPCGSolver : Solver {
         MSPCG_HIP(hipMemsetAsync(pp.data, 0, (size_t)12 * c->Nh * sizeof(double2), st));
         if (launch_dot2(z.data, r.data, r.data, c->Nh, c->partials, npb, st)) return MSPCG_EHIP;
         if (launch_fpcg_beta(c->sc, c->partials, (int)npb, st)) return MSPCG_EHIP;
-        if (launch_xpay(pp.data, z.data, c->Nh, c->sc, 0, st)) return MSPCG_EHIP;
         return 0;
     }
     int init(hipStream_t st) override {
@@ -257,18 +252,15 @@ struct MSPCGSolver : Solver {
         }
         return 0;
     }
+    // p = z + beta p ; q = A p ; x += alpha p ; r -= alpha q (fused, q kept) ;
+    // z = K r ; flexible beta from <z, r> and <z, q>
     int iterate(hipStream_t st) override {
         int e;
-        if ((e = op_A<F64>(c, q, cfield(pp), c->partials, &c->sc->done, st))) return e;
-        if (launch_cg_alpha(c->sc, c->partials, (int)nph, st, 1)) return MSPCG_EHIP;
-        if (launch_cg_update_xr(x.data, r.data, pp.data, q.data, c->Nh, c->sc, c->partials, npb,
-                                st))
-            return MSPCG_EHIP;
-        if (launch_cg_beta(c->sc, c->partials, (int)npb, c->hist, cap, st)) return MSPCG_EHIP;
+        if ((e = cg_step<F64>(c, x, r, pp, q, cfield(z), true, true, &c->sc->done, st))) return e;
+        if (launch_cg_beta(c->sc, c->partials, (int)nph, c->hist, cap, st)) return MSPCG_EHIP;
         if ((e = precond_apply_flag<S>(c, l, cfield(r), z, &c->sc->done, st))) return e;
         if (launch_dot2(z.data, r.data, q.data, c->Nh, c->partials, npb, st)) return MSPCG_EHIP;
         if (launch_fpcg_beta(c->sc, c->partials, (int)npb, st)) return MSPCG_EHIP;
-        if (launch_xpay(pp.data, z.data, c->Nh, c->sc, 0, st)) return MSPCG_EHIP;
         return 0;
     }
     int after_poll(hipStream_t st) override {
@@ -352,15 +344,12 @@ struct MixedSolver : Solver {
         true_rr = rr;
         return push(c, st, s);
     }
+    // the FP32 CG step, fused as in plain CG
     int iterate(hipStream_t st) override {
         int e;
-        if ((e = op_A<F32>(c, qs, cfield(ps), c->partials, &c->sc->done, st))) return e;
-        if (launch_cg_alpha(c->sc, c->partials, (int)nph, st, 0)) return MSPCG_EHIP;
-        if (launch_cg_update_xr32(xs.data, rs.data, ps.data, qs.data, c->Nh, c->sc, c->partials,
-                                  npb, st))
-            return MSPCG_EHIP;
-        if (launch_cg_beta(c->sc, c->partials, (int)npb, c->hist, cap, st)) return MSPCG_EHIP;
-        if (launch_xpay32(ps.data, rs.data, c->Nh, c->sc, st)) return MSPCG_EHIP;
+        if ((e = cg_step<F32>(c, xs, rs, ps, qs, cfield(rs), false, false, &c->sc->done, st)))
+            return e;
+        if (launch_cg_beta(c->sc, c->partials, (int)nph, c->hist, cap, st)) return MSPCG_EHIP;
         return 0;
     }
     int after_poll(hipStream_t st) override {
@@ -385,13 +374,13 @@ struct MixedSolver : Solver {
             }
             if (launch_convert<F64, F32>(cfield(r), rs, c->Nh, st)) return MSPCG_EHIP;
             rr_update = true_rr;
-            // keep the search direction: p = r + beta p with beta = |r_true|^2 / |r_prev|^2
+            // keep the search direction: the next step forms p = r + beta p with
+            // beta = |r_true|^2 / |r_prev|^2
             s.beta = s.rr > 0 ? s.beta * true_rr / s.rr : 0.0;
             s.rr = true_rr;
             s.done = 0;
             set_target();
             if ((e = push(c, st, s))) return e;
-            if (launch_xpay32(ps.data, rs.data, c->Nh, c->sc, st)) return MSPCG_EHIP;
         }
         return 0;
     }
