@@ -11,6 +11,7 @@
 // so only the 2x3 half spinor h is multiplied by the link.
 //   e_x = -i sigma_x, e_y = -i sigma_y, e_z = -i sigma_z, e_t = 1.
 #pragma once
+#include <type_traits>
 #include <utility>
 
 #include "common.h"
@@ -128,21 +129,50 @@ __device__ __forceinline__ void dir_apply(const cx<typename S::real> (&p)[12],
     reconstruct<MU, SIG>(w, acc);
 }
 
-template <int MU, int FWD>
-__device__ __forceinline__ bool neighbour(const HopGeom& g, const int gc[4], long& cb) {
-    int c[4] = {gc[0] - g.in.off[0], gc[1] - g.in.off[1], gc[2] - g.in.off[2], gc[3] - g.in.off[3]};
-    c[MU] += FWD ? 1 : -1;
-    // directions in the periodic mask wrap (the box spans the lattice there);
-    // all others drop hops whose source lies outside the input box
-    if ((g.periodic >> MU) & 1) {
-        if (c[MU] < 0) c[MU] += g.in.E[MU];
-        if (c[MU] >= g.in.E[MU]) c[MU] -= g.in.E[MU];
-    }
+// Input-box position of one output site, set up once per thread so that each
+// neighbour costs a few 32-bit integer operations: lex index in the input box,
+// the coordinates, and a mask of the dimensions whose coordinate lies in it.
+struct InPos {
+    int c[4];
+    int st[4];  // lex strides of the input box
+    int lex;
+    int inr;    // bit m: 0 <= c[m] < E[m]
+};
+
+__device__ __forceinline__ InPos in_position(const HopGeom& g, const int gc[4]) {
+    InPos q;
+    q.st[0] = 1;
+    q.st[1] = g.in.E[0];
+    q.st[2] = g.in.E[0] * g.in.E[1];
+    q.st[3] = q.st[2] * g.in.E[2];
+    q.lex = 0;
+    q.inr = 0;
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-        if (!((g.periodic >> m) & 1) && (c[m] < 0 || c[m] >= g.in.E[m])) return false;
-    cb = box_cb(g.in, c);
-    return true;
+    for (int m = 0; m < 4; ++m) {
+        q.c[m] = gc[m] - g.in.off[m];
+        q.lex += q.c[m] * q.st[m];
+        if (q.c[m] >= 0 && q.c[m] < g.in.E[m]) q.inr |= 1 << m;
+    }
+    return q;
+}
+
+// Checkerboard index of the neighbour in direction +/-MU.  Directions in the
+// periodic mask wrap (the box spans the lattice there); all others drop hops
+// whose source lies outside the input box.
+template <int MU, int FWD>
+__device__ __forceinline__ bool neighbour(const HopGeom& g, const InPos& q, long& cb) {
+    const int E = g.in.E[MU];
+    const int cm = q.c[MU] + (FWD ? 1 : -1);
+    int nl = q.lex + (FWD ? q.st[MU] : -q.st[MU]);
+    bool ok = (q.inr | (1 << MU)) == 15;
+    if ((g.periodic >> MU) & 1) {
+        if (cm >= E) nl -= E * q.st[MU];
+        if (cm < 0) nl += E * q.st[MU];
+    } else {
+        ok = ok && cm >= 0 && cm < E;
+    }
+    cb = nl >> 1;
+    return ok;
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (linear id mod 8),
@@ -200,8 +230,10 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
     using E = typename S::elem;
     constexpr int SPB = 256 / LS;
     constexpr int SITE_STRIDE = LS * 12 + 1;  // LDS row padding against bank conflicts
-    constexpr int NCH = 72 * (int)sizeof(E) / 16;  // 16-byte chunks of one site's links
-    constexpr int LSTR = NCH + 1;                  // padded site stride (chunks)
+    // FP16 links are decoded to FP32 once, when staged; LE is the LDS entry
+    using LE = typename std::conditional<S::has_scale, nt_f2, E>::type;
+    constexpr int NCH = 72 * (int)sizeof(E) / 16;   // 16-byte chunks of one site's links
+    constexpr int LSTR = 72 * (int)sizeof(LE) / 16 + 1;  // padded LDS site stride (chunks)
     constexpr bool LDSL = SPB * LSTR * 16 <= 40 * 1024;
     constexpr bool EPI = EPH || EPA;
     constexpr int EPI_BYTES = EPI ? SPB * SITE_STRIDE * (int)sizeof(cx<T>) : 16;
@@ -259,10 +291,20 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
         if constexpr (LDSL) {
             const nt_u4* src = reinterpret_cast<const nt_u4*>(gl);
             for (int j = s; j < NCH; j += LS) {
+                nt_u4 v;
                 if constexpr (MSPCG_HOP_NT)
-                    lnk[sl * LSTR + j] = __builtin_nontemporal_load(src + j);
+                    v = __builtin_nontemporal_load(src + j);
                 else
-                    lnk[sl * LSTR + j] = src[j];
+                    v = src[j];
+                if constexpr (S::has_scale) {
+                    const cx<float> e0 = h2f(v.x, 1.f), e1 = h2f(v.y, 1.f);
+                    const cx<float> e2 = h2f(v.z, 1.f), e3 = h2f(v.w, 1.f);
+                    nt_f4* dst = reinterpret_cast<nt_f4*>(lnk + sl * LSTR + 2 * j);
+                    dst[0] = nt_f4{e0.re, e0.im, e1.re, e1.im};
+                    dst[1] = nt_f4{e2.re, e2.im, e3.re, e3.im};
+                } else {
+                    lnk[sl * LSTR + j] = v;
+                }
             }
         }
     }
@@ -273,6 +315,7 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
     for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
     if (active) {
         const long ibase = (long)d * g.in.Vh;
+        const InPos ip = in_position(g, gc);
         // forward terms use (1 - g) and backward (1 + g); the dagger swaps them
         constexpr int SF = DAG ? 1 : -1;
         constexpr int SB = -SF;
@@ -289,7 +332,7 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
                 constexpr int MU = D / 2;
                 constexpr bool FWD = (D % 2) == 0;
                 long n = 0;
-                ok[j] = neighbour<MU, FWD ? 1 : 0>(g, gc, n);
+                ok[j] = neighbour<MU, FWD ? 1 : 0>(g, ip, n);
                 if (ok[j]) load_raw_at<S>(a.in, (ibase + n) * LS, s, LS, raw[j]);
             });
             sfor<PF>([&](auto j) {
@@ -302,9 +345,9 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
                     decode_raw<S>(raw[j], p);
                     cx<T> u[9];
                     if constexpr (LDSL) {
-                        const E* le = reinterpret_cast<const E*>(lnk + sl * LSTR) + LD;
+                        const LE* le = reinterpret_cast<const LE*>(lnk + sl * LSTR) + LD;
 #pragma unroll
-                        for (int k = 0; k < 9; ++k) u[k] = elem_cx<S>(le[k]);
+                        for (int k = 0; k < 9; ++k) u[k] = {(T)le[k].x, (T)le[k].y};
                     } else {
 #pragma unroll
                         for (int k = 0; k < 9; ++k) u[k] = load_link<S, MSPCG_HOP_NT>(gl + LD + k);
