@@ -219,11 +219,15 @@ __device__ __forceinline__ void sfor(F&& f) {
     sfor_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-// EPH / EPA: the hop-output / aux program mixes s (needs the LDS exchange;
-// separate flags keep the register footprint of the common cases low).  The links of the
-// workgroup's sites are staged in LDS with coalesced 16-byte loads (one load
-// per 16 bytes of links instead of one per element and lane) when they fit;
-// the epilogue reuses that LDS after the direction loop.
+// 5D programs on the hop output (ph) and on aux (pa): a scale is applied in
+// registers; a single bidiagonal step (M5, M5^+, B^+) by exchanging each
+// (site, s) value with its s-1 / s+1 neighbour through LDS; longer programs
+// (X = B M5^-1 and its adjoint) run as per-(site, component) chains over s in
+// LDS, selected at compile time by EPH / EPA because the chain's s-vector
+// raises the register footprint.  The links of the workgroup's sites are
+// staged in LDS with coalesced 16-byte loads (one load per 16 bytes of links
+// instead of one per element and lane) when they fit; the epilogue reuses
+// that LDS after the direction loop.
 template <class S, int LS, bool DAG, bool EPH, bool EPA, bool CG = false>
 __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S> a) {
     using T = typename S::real;
@@ -235,8 +239,9 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
     constexpr int NCH = 72 * (int)sizeof(E) / 16;   // 16-byte chunks of one site's links
     constexpr int LSTR = 72 * (int)sizeof(LE) / 16 + 1;  // padded LDS site stride (chunks)
     constexpr bool LDSL = SPB * LSTR * 16 <= 40 * 1024;
-    constexpr bool EPI = EPH || EPA;
-    constexpr int EPI_BYTES = EPI ? SPB * SITE_STRIDE * (int)sizeof(cx<T>) : 16;
+    // the s-exchange array serves both the chain programs (EPH/EPA) and the
+    // single-step programs applied by neighbour exchange
+    constexpr int EPI_BYTES = SPB * SITE_STRIDE * (int)sizeof(cx<T>);
     constexpr int LNK_BYTES = LDSL ? SPB * LSTR * 16 : 16;
     constexpr int LDS_BYTES = EPI_BYTES > LNK_BYTES ? EPI_BYTES : LNK_BYTES;
     __shared__ __attribute__((aligned(16))) unsigned char smem[LDS_BYTES];
@@ -359,30 +364,63 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
     }
 
     const long obase = ((long)d * g.out.Vh + cb) * LS;
-    cx<T> res[12];
     const T mf = (T)a.mf;
-    if (!EPH || a.ph.identity) {
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            const T sc = (T)(c < 6 ? a.ph.scale[0] : a.ph.scale[1]);
-            res[c] = {acc[c].re * sc, acc[c].im * sc};
-        }
-    } else {
-        if constexpr (LDSL) __syncthreads();  // every wave is done with the staged links
+    // one bidiagonal step v_s <- sc (v_s + a v_{s-/+1}), the -mf corner closing
+    // the s direction; entered by all threads (uniform arguments)
+    auto bidi1 = [&](const FiveDProg& P, cx<T>(&v)[12]) {
+        __syncthreads();  // LDS free: staged links or an earlier phase
         if (active) {
 #pragma unroll
-            for (int c = 0; c < 12; ++c) lds[sl * SITE_STRIDE + s * 12 + c] = acc[c];
+            for (int c = 0; c < 12; ++c) lds[sl * SITE_STRIDE + s * 12 + c] = v[c];
         }
         __syncthreads();
+        if (active) {
+            const T av = (T)P.a[0];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const bool up = c < 6;
+                const bool below = up != (P.dag[0] != 0);
+                const bool corner = below ? s == 0 : s == LS - 1;
+                const int s2 = below ? (corner ? LS - 1 : s - 1) : (corner ? 0 : s + 1);
+                const cx<T> nb = lds[sl * SITE_STRIDE + s2 * 12 + c];
+                const T f = corner ? -(av * mf) : av;
+                const T sc = (T)(up ? P.scale[0] : P.scale[1]);
+                v[c] = {sc * (v[c].re + f * nb.re), sc * (v[c].im + f * nb.im)};
+            }
+        }
+    };
+    // chain program over s for every (site, component), in place in LDS
+    auto chains = [&](const FiveDProg& P) {
         for (int ch = threadIdx.x; ch < SPB * 12; ch += blockDim.x) {
             const int csl = ch / 12, comp = ch - csl * 12;
             cx<T> v[LS];
 #pragma unroll
             for (int t = 0; t < LS; ++t) v[t] = lds[csl * SITE_STRIDE + t * 12 + comp];
-            apply_prog<LS, T>(a.ph, comp < 6, mf, v);
+            apply_prog<LS, T>(P, comp < 6, mf, v);
 #pragma unroll
             for (int t = 0; t < LS; ++t) lds[csl * SITE_STRIDE + t * 12 + comp] = v[t];
         }
+    };
+
+    cx<T> res[12];
+    if (a.ph.identity) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const T sc = (T)(c < 6 ? a.ph.scale[0] : a.ph.scale[1]);
+            res[c] = {acc[c].re * sc, acc[c].im * sc};
+        }
+    } else if (!EPH) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) res[c] = acc[c];
+        bidi1(a.ph, res);
+    } else {
+        __syncthreads();  // every wave is done with the staged links
+        if (active) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) lds[sl * SITE_STRIDE + s * 12 + c] = acc[c];
+        }
+        __syncthreads();
+        chains(a.ph);
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < 12; ++c) res[c] = lds[sl * SITE_STRIDE + s * 12 + c];
@@ -403,12 +441,19 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
             }
             if (in) load_spinor_at<S>(a.aux, ((long)d * g.aux.Vh + box_cb(g.aux, ac)) * LS, s, LS, x);
         }
-        if (!EPA || a.pa.identity) {
+        if (a.pa.identity) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 const T sc = (T)(c < 6 ? a.pa.scale[0] : a.pa.scale[1]);
                 res[c].re += sc * x[c].re;
                 res[c].im += sc * x[c].im;
+            }
+        } else if (!EPA) {
+            bidi1(a.pa, x);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                res[c].re += x[c].re;
+                res[c].im += x[c].im;
             }
         } else {
             __syncthreads();  // the hop epilogue may still read lds
@@ -417,15 +462,7 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
                 for (int c = 0; c < 12; ++c) lds[sl * SITE_STRIDE + s * 12 + c] = x[c];
             }
             __syncthreads();
-            for (int ch = threadIdx.x; ch < SPB * 12; ch += blockDim.x) {
-                const int csl = ch / 12, comp = ch - csl * 12;
-                cx<T> v[LS];
-#pragma unroll
-                for (int t = 0; t < LS; ++t) v[t] = lds[csl * SITE_STRIDE + t * 12 + comp];
-                apply_prog<LS, T>(a.pa, comp < 6, mf, v);
-#pragma unroll
-                for (int t = 0; t < LS; ++t) lds[csl * SITE_STRIDE + t * 12 + comp] = v[t];
-            }
+            chains(a.pa);
             __syncthreads();
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
@@ -482,15 +519,21 @@ static void launch_ls(const HopArgs<S>& a, int ndom, bool dag, hipStream_t st) {
     constexpr int SPB = 256 / LS;
     dim3 grid((unsigned)((a.g.out.Vh + SPB - 1) / SPB), (unsigned)ndom);
     dim3 block(SPB * LS);
-    const bool eph = !a.ph.identity;
-    const bool epa = a.has_aux && !a.pa.identity;
+    // programs of at most one bidiagonal step are applied by s-exchange
+    auto chain = [](const FiveDProg& P) {
+        return !P.identity && !(P.nsteps == 1 && P.kind[0] == STEP_BIDI);
+    };
+    const bool eph = chain(a.ph);
+    const bool epa = a.has_aux && chain(a.pa);
     if (a.cg_r.data) {
         // the fused CG update only follows the last (dagger) hop of A in FP64
         // and FP32; the epilogue variant also handles identity programs
         if constexpr (S::has_scale) {
             return;
         } else {
-            if (dag)
+            if (dag && !eph && !epa)
+                hipLaunchKernelGGL((hop_kernel<S, LS, true, false, false, true>), grid, block, 0, st, a);
+            else if (dag)
                 hipLaunchKernelGGL((hop_kernel<S, LS, true, true, true, true>), grid, block, 0, st, a);
             return;
         }
