@@ -42,26 +42,36 @@ WORKLOADS = {
 DEFAULT = "dwf_moebius_24c48_ls16"
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop64_dwf_moebius_24c48_ls16_traffic.json")
-KERNEL_SOURCES = ["paper_1804_08593_amd/csrc/hop_impl.h", "paper_1804_08593_amd/csrc/hop_f64.hip",
-                  "paper_1804_08593_amd/csrc/common.h", "paper_1804_08593_amd/csrc/fived.h"]
+# committed rocprofv3 counter summaries (HBM bytes per launch of a kernel
+# class), valid only for the kernel sources they were taken on
+KERNEL_SOURCES = {
+    "hop64": ["hop_impl.h", "hop_f64.hip", "common.h", "fived.h", "api.hip"],
+    "hopdom": ["hop_impl.h", "hop_f16.hip", "common.h", "fived.h", "precond.hip"],
+}
 
 
-def kernel_source_hash() -> str:
+def traffic_file(cls: str, workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"{cls}_{workload}_traffic.json")
+
+
+def kernel_source_hash(cls: str) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+    for f in KERNEL_SOURCES[cls]:
+        h.update(open(os.path.join(ROOT, "paper_1804_08593_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per FP64 hop launch from the committed rocprofv3 counter
-    summary, or None when it is missing or was taken on other kernel sources."""
+def measured_traffic(cls: str, workload: str):
+    """HBM bytes per launch of kernel class `cls` from the committed rocprofv3
+    counter summary, or None when it is missing or was taken on other kernel
+    sources."""
+    if cls not in KERNEL_SOURCES:
+        return None
     try:
-        t = json.load(open(TRAFFIC_FILE))
+        t = json.load(open(traffic_file(cls, workload)))
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_hash") != kernel_source_hash() or t.get("workload") != workload:
+    if t.get("kernel_source_hash") != kernel_source_hash(cls) or t.get("workload") != workload:
         return None
     return t.get("traffic_bytes_per_launch")
 
@@ -215,7 +225,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(dom_gbs, 1) if dom_gbs else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(dom_gbs / HBM_PEAK_GBS, 4) if dom_gbs else None,
-                     "traffic": measured_traffic(args.workload) if dom == "hop64" else None},
+                     "traffic": measured_traffic(dom, args.workload)},
     }
     if run_mx:
         mx_s = float(np.median([r["mixed"]["seconds"] for r in results]))
