@@ -153,7 +153,8 @@ enum {
     MSPCG_KC_FIVED = 3,  /* 5D-only kernels */
     MSPCG_KC_BLAS = 4,   /* vector updates, reductions, conversions */
     MSPCG_KC_HOPCG = 5,  /* last hop of A with the CG vector update fused in (FP64/FP32) */
-    MSPCG_KC_COUNT = 6
+    MSPCG_KC_HOPDOMCG = 6, /* last block-domain hop of A_s with the local CG update fused in */
+    MSPCG_KC_COUNT = 7
 };
 
 typedef struct {

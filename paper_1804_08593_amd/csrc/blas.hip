@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void fived_kernel(FiveDArgs<S> a) {
         load_spinor_at<S>(a.in, ib, s, LS, v);
         if (a.xp_src.data) {
             // search-direction update p = src + beta p, written back in place
-            const T b = (T)a.xp_sc->beta;
+            const T b = (T)(a.xp_beta ? a.xp_beta[d] : a.xp_sc->beta);
             cx<T> r[12];
             load_spinor_at<S>(a.xp_src, ib, s, LS, r);
 #pragma unroll
@@ -302,9 +302,22 @@ __global__ void accum32_kernel(double2* x, float2* xs, long n, int Ls) {
     }
 }
 
+// y = 0 (a kernel, not a memset node, so it may sit in a captured graph)
+__global__ void zero_kernel(double2* y, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x)
+        y[i] = make_double2(0.0, 0.0);
+}
+
 int last_error() { return hipGetLastError() == hipSuccess ? 0 : -2; }
 
 }  // namespace
+
+int launch_zero(double2* y, long N, hipStream_t st) {
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blas_grid_x(12 * N)), dim3(kThreads), 0, st, y,
+                       12 * N);
+    return last_error();
+}
 
 int launch_cg_update_xr32(float2* x, float2* r, const float2* p, const float2* q, long N,
                           const DevScalars* sc, double* partials, long nparts, hipStream_t st) {

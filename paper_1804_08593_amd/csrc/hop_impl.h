@@ -478,7 +478,7 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
         double n2 = 0;
         if (active) {
             if (a.cg_keep_out) store_spinor_at<S, MSPCG_HOP_NT>(a.out, obase, s, LS, res);
-            const T al = (T)a.cg_sc->alpha;
+            const T al = (T)(a.cg_alpha ? a.cg_alpha[d] : a.cg_sc->alpha);
             cx<T> v[12];
             load_spinor_at<S>(cfield(a.cg_r), obase, s, LS, v);
 #pragma unroll
@@ -490,11 +490,16 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
             store_spinor_at<S>(a.cg_r, obase, s, LS, v);
             cx<T> pv[12];
             load_spinor_at<S>(a.cg_p, obase, s, LS, pv);
-            load_spinor_at<S>(cfield(a.cg_x), obase, s, LS, v);
+            if (a.cg_first) {
 #pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                v[c].re += al * pv[c].re;
-                v[c].im += al * pv[c].im;
+                for (int c = 0; c < 12; ++c) v[c] = {al * pv[c].re, al * pv[c].im};
+            } else {
+                load_spinor_at<S>(cfield(a.cg_x), obase, s, LS, v);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    v[c].re += al * pv[c].re;
+                    v[c].im += al * pv[c].im;
+                }
             }
             store_spinor_at<S>(a.cg_x, obase, s, LS, v);
         }
@@ -526,17 +531,13 @@ static void launch_ls(const HopArgs<S>& a, int ndom, bool dag, hipStream_t st) {
     const bool eph = chain(a.ph);
     const bool epa = a.has_aux && chain(a.pa);
     if (a.cg_r.data) {
-        // the fused CG update only follows the last (dagger) hop of A in FP64
-        // and FP32; the epilogue variant also handles identity programs
-        if constexpr (S::has_scale) {
-            return;
-        } else {
-            if (dag && !eph && !epa)
-                hipLaunchKernelGGL((hop_kernel<S, LS, true, false, false, true>), grid, block, 0, st, a);
-            else if (dag)
-                hipLaunchKernelGGL((hop_kernel<S, LS, true, true, true, true>), grid, block, 0, st, a);
-            return;
-        }
+        // the fused CG update only follows the last (dagger) hop of A; the
+        // chain variant also handles single-step programs
+        if (dag && !eph && !epa)
+            hipLaunchKernelGGL((hop_kernel<S, LS, true, false, false, true>), grid, block, 0, st, a);
+        else if (dag)
+            hipLaunchKernelGGL((hop_kernel<S, LS, true, true, true, true>), grid, block, 0, st, a);
+        return;
     }
 #define MSPCG_HOP_LAUNCH(D, H, A) \
     hipLaunchKernelGGL((hop_kernel<S, LS, D, H, A>), grid, block, 0, st, a)
@@ -556,7 +557,7 @@ static void launch_ls(const HopArgs<S>& a, int ndom, bool dag, hipStream_t st) {
 
 template <class S>
 int launch_hop(const HopArgs<S>& a, int Ls, int ndom, bool dag, hipStream_t st) {
-    if (a.cg_r.data && (S::has_scale || !dag || ndom != 1)) return -1;
+    if (a.cg_r.data && (!dag || !a.partials)) return -1;
     switch (Ls) {
 #define MSPCG_CASE(L) \
     case L: launch_ls<S, L>(a, ndom, dag, st); break;

@@ -35,14 +35,18 @@ struct HopArgs {
     const int* done;   // optional: skip the launch when *done != 0
     int xcd_remap;     // map workgroups so each XCD walks a contiguous site range
     int tile[4];       // nonzero: traverse output sites in 4D tiles of this extent
-    // optional CG update fused after the output is formed (whole-lattice hops):
-    //   r -= alpha out ; x += alpha p ; partials = |r|^2 ; out is stored only
-    //   when cg_keep_out.  alpha is read from cg_sc.
+    // optional CG update fused after the output is formed (the last hop of A,
+    // whole lattice or block domains):
+    //   r -= alpha out ; x += alpha p (x = alpha p when cg_first) ;
+    //   partials = |r|^2 ; out is stored only when cg_keep_out.
+    //   alpha is cg_alpha[domain] when given, else cg_sc->alpha.
     Field<S> cg_r;
     Field<S> cg_x;
     CField<S> cg_p;
     const DevScalars* cg_sc;
+    const double* cg_alpha;
     int cg_keep_out;
+    int cg_first;
 };
 
 template <class S>
@@ -61,10 +65,12 @@ struct FiveDArgs {
     double* partials;
     const int* done;
     // optional search-direction update before the program: in = src + beta in,
-    // written back through xp_in (the same field as `in`); beta from xp_sc
+    // written back through xp_in (the same field as `in`); beta is
+    // xp_beta[domain] when given, else xp_sc->beta
     CField<S> xp_src;
     Field<S> xp_in;
     const DevScalars* xp_sc;
+    const double* xp_beta;
 };
 template <class S>
 int launch_fived(const FiveDArgs<S>& a, int Ls, int ndom, hipStream_t st);
@@ -140,6 +146,7 @@ int launch_copy_norm(double2* dst, const double2* src, long N, double* partials,
 int launch_dot2(const double2* z, const double2* r, const double2* q, long N, double* partials,
                 long nparts, hipStream_t st);
 int launch_axpy(double2* y, const double2* x, double a, long N, hipStream_t st);
+int launch_zero(double2* y, long N, hipStream_t st);
 
 // FP32 iterations of the mixed-precision CG
 int launch_cg_update_xr32(float2* x, float2* r, const float2* p, const float2* q, long N,

@@ -146,64 +146,6 @@ __global__ void inner_start_kernel(CField<F64> r, Field<S> rho, Field<S> p, DomG
     block_reduce_store(n2, partials + (long)d * gridDim.x + blockIdx.x);
 }
 
-// z += a p (z = a p on the first step) ; rho -= a w ; |rho|^2 partials
-template <class S>
-__global__ void inner_update_kernel(Field<S> z, Field<S> rho, CField<S> p, CField<S> w, long n_dom,
-                                    InnerScalars sc, int first, double* partials, const int* done) {
-    if (done && *done) return;
-    using T = typename S::real;
-    const int d = blockIdx.y;
-    const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    double n2 = 0;
-    if (j < n_dom) {
-        const long i = (long)d * n_dom + j;
-        const T a = (T)sc.a[d];
-        const int ls = p.ls, s = entry_lane(i, ls);
-        const long ib = i - s;
-        cx<T> pv[12], wv[12], zv[12], rv[12];
-        load_spinor_at<S>(p, ib, s, ls, pv);
-        load_spinor_at<S>(w, ib, s, ls, wv);
-        load_spinor_at<S>(cfield(rho), ib, s, ls, rv);
-        if (!first) load_spinor_at<S>(cfield(z), ib, s, ls, zv);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            if (first) zv[k] = {0, 0};
-            zv[k].re += a * pv[k].re;
-            zv[k].im += a * pv[k].im;
-            rv[k].re -= a * wv[k].re;
-            rv[k].im -= a * wv[k].im;
-            n2 += (double)rv[k].re * rv[k].re + (double)rv[k].im * rv[k].im;
-        }
-        store_spinor_at<S>(z, ib, s, ls, zv);
-        store_spinor_at<S>(rho, ib, s, ls, rv);
-    }
-    block_reduce_store(n2, partials + (long)d * gridDim.x + blockIdx.x);
-}
-
-// p = rho + beta p
-template <class S>
-__global__ void inner_xpay_kernel(Field<S> p, CField<S> rho, long n_dom, InnerScalars sc,
-                                  const int* done) {
-    if (done && *done) return;
-    using T = typename S::real;
-    const int d = blockIdx.y;
-    const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n_dom) return;
-    const long i = (long)d * n_dom + j;
-    const T b = (T)sc.beta[d];
-    const int ls = p.ls, s = entry_lane(i, ls);
-    const long ib = i - s;
-    cx<T> pv[12], rv[12];
-    load_spinor_at<S>(cfield(p), ib, s, ls, pv);
-    load_spinor_at<S>(rho, ib, s, ls, rv);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-        pv[k].re = rv[k].re + b * pv[k].re;
-        pv[k].im = rv[k].im + b * pv[k].im;
-    }
-    store_spinor_at<S>(p, ib, s, ls, pv);
-}
-
 int last_error() { return hipGetLastError() == hipSuccess ? 0 : MSPCG_EHIP; }
 
 }  // namespace
@@ -282,14 +224,48 @@ static int periodic_mask(const Domains& D) {
     return m;
 }
 
+// Sites of box a inside box b (both parities).
+static double box_overlap(const Box& a, const Box& b) {
+    double v = 1;
+    for (int m = 0; m < 4; ++m) {
+        const int lo = a.off[m] > b.off[m] ? a.off[m] : b.off[m];
+        const int hi = a.off[m] + a.E[m] < b.off[m] + b.E[m] ? a.off[m] + a.E[m] : b.off[m] + b.E[m];
+        v *= hi > lo ? hi - lo : 0;
+    }
+    return v;
+}
+
+// Sites of the input box that a hop onto the output box reads: the output
+// box itself and the one-site face slabs around it (no edges or corners).
+static double hop_read_sites(const Box& in, const Box& out) {
+    double n = box_overlap(in, out);
+    for (int m = 0; m < 4; ++m)
+        for (int side = 0; side < 2; ++side) {
+            Box f = out;
+            f.off[m] = side ? out.off[m] + out.E[m] : out.off[m] - 1;
+            f.E[m] = 1;
+            n += box_overlap(in, f);
+        }
+    return n;
+}
+
 template <class S>
 static int dom_hop(mspcg_ctx* c, Field<S> out, const Box& bout, CField<S> in, const Box& bin,
                    int out_par, bool dag, const FiveDProg& ph, const CField<S>* aux,
                    const Box& baux, const FiveDProg& pa, double* partials, const int* done,
-                   hipStream_t st) {
+                   hipStream_t st, const HopArgs<S>* cg = nullptr) {
     const Domains& D = c->dom;
     HopArgs<S> a;
     memset(&a, 0, sizeof(a));
+    if (cg) {
+        // fused local CG update (rho -= a w, z += a p) on the block interior
+        a.cg_r = cg->cg_r;
+        a.cg_x = cg->cg_x;
+        a.cg_p = cg->cg_p;
+        a.cg_alpha = cg->cg_alpha;
+        a.cg_first = cg->cg_first;
+        a.cg_keep_out = 0;
+    }
     a.in = in;
     a.out = out;
     if (aux) a.aux = *aux;
@@ -309,16 +285,22 @@ static int dom_hop(mspcg_ctx* c, Field<S> out, const Box& bout, CField<S> in, co
     a.done = done;
     a.xcd_remap = c->tune.xcd_remap;
     pick_tile(c->tune.tile[prec_index<S>()], bout, a.tile);
-    const double bytes = (double)D.ndom * c->Ls *
-                             (double)(bout.Vh + bin.Vh + (aux ? baux.Vh : 0)) * S::bytes_spinor +
+    // spinor entries per s moved (one parity): out, the input sites the hop
+    // reads, aux at the output sites; the fused update reads rho, p (z unless
+    // first) and writes rho, z in place of out
+    double entries = (double)bout.Vh + hop_read_sites(bin, bout) / 2 +
+                     (aux ? box_overlap(baux, bout) / 2 : 0);
+    if (cg) entries += (double)bout.Vh * (cg->cg_first ? 3 : 4);
+    const double bytes = (double)D.ndom * c->Ls * entries * S::bytes_spinor +
                          (double)D.ndom * bout.Vh * 8 * S::bytes_link;
-    Timed t(c, MSPCG_KC_HOPDOM, bytes, st);
+    Timed t(c, cg ? MSPCG_KC_HOPDOMCG : MSPCG_KC_HOPDOM, bytes, st);
     return launch_hop<S>(a, c->Ls, D.ndom, dag, st);
 }
 
 template <class S>
 static int dom_fived(mspcg_ctx* c, Field<S> out, CField<S> in, long Vh, const FiveDProg& p,
-                     const int* done, hipStream_t st) {
+                     const int* done, hipStream_t st, const Field<S>* xp_in = nullptr,
+                     CField<S> xp_src = {}, const double* xp_beta = nullptr) {
     FiveDArgs<S> a;
     memset(&a, 0, sizeof(a));
     a.in = in;
@@ -328,7 +310,13 @@ static int dom_fived(mspcg_ctx* c, Field<S> out, CField<S> in, long Vh, const Fi
     a.mf = c->act.mf;
     a.partials = nullptr;
     a.done = done;
-    Timed t(c, MSPCG_KC_FIVED, (double)c->dom.ndom * Vh * c->Ls * S::bytes_spinor * 2, st);
+    if (xp_in) {  // in = src + beta[domain] in, written back, before the program
+        a.xp_in = *xp_in;
+        a.xp_src = xp_src;
+        a.xp_beta = xp_beta;
+    }
+    Timed t(c, MSPCG_KC_FIVED, (double)c->dom.ndom * Vh * c->Ls * S::bytes_spinor * (xp_in ? 4 : 2),
+            st);
     return launch_fived<S>(a, c->Ls, c->dom.ndom, st);
 }
 
@@ -372,6 +360,63 @@ int block_A(mspcg_ctx* c, Field<S> w, CField<S> p, double* partials, const int* 
                       &yc, D.pad2, P.M5dag, nullptr, done, st);
 }
 
+// One local CG step on every block with the vector updates fused into the
+// block operator: p = rho + beta p rides on t = B p (it > 0), alpha =
+// gam / |Mhat_D p|^2 per block is formed after the Mhat half, and the last
+// hop does rho -= alpha w, z += alpha p (z = alpha p when it == 0) with the
+// per-block |rho|^2 partials ([ndom][hop_grid_x(interior.Vh)]); w is never
+// stored.  pq_partials receive |Mhat_D p|^2 laid out [ndom][hop_np].
+template <class S>
+static int block_cg_step(mspcg_ctx* c, Field<S> p, Field<S> rho, Field<S> z,
+                         const InnerScalars& sc, int it, double* part, long hop_np,
+                         const int* done, hipStream_t st) {
+    const Domains& D = c->dom;
+    const int Ls = c->Ls;
+    const std::string pf = std::string("dom") + (std::is_same<S, F16>::value ? "16." : std::is_same<S, F32>::value ? "32." : "64.");
+    Field<S> t = half_field<S>(c, pf + "t", (long)D.ndom * D.interior.Vh * Ls);
+    Field<S> u = half_field<S>(c, pf + "u", (long)D.ndom * D.pad1.Vh * Ls);
+    Field<S> y = half_field<S>(c, pf + "y", (long)D.ndom * D.pad2.Vh * Ls);
+    Field<S> v = half_field<S>(c, pf + "v", (long)D.ndom * D.pad1.Vh * Ls);
+    if (!t.data || !u.data || !y.data || !v.data) return MSPCG_ENOMEM;
+    const Progs& P = c->pr;
+    FiveDProg m14;
+    memset(&m14, 0, sizeof(m14));
+    m14.scale[0] = m14.scale[1] = -0.25;
+    m14.identity = 1;
+    const CField<S> pc = cfield(p);
+    int e;
+    if (it > 0) {
+        if ((e = dom_fived<S>(c, t, pc, D.interior.Vh, P.B, done, st, &p, cfield(rho), sc.beta)))
+            return e;
+    } else if ((e = dom_fived<S>(c, t, pc, D.interior.Vh, P.B, done, st))) {
+        return e;
+    }
+    if ((e = dom_hop<S>(c, u, D.pad1, cfield(t), D.interior, 1, false, P.X, nullptr, D.interior,
+                        P.id, nullptr, done, st)))
+        return e;
+    if ((e = dom_hop<S>(c, y, D.pad2, cfield(u), D.pad1, 0, false, m14, &pc, D.interior, P.M5,
+                        part, done, st)))
+        return e;
+    hipLaunchKernelGGL(inner_alpha, dim3(D.ndom), dim3(kThreads), 0, st, sc, part, (int)hop_np,
+                       done);
+    if (last_error()) return MSPCG_EHIP;
+    if ((e = dom_hop<S>(c, v, D.pad1, cfield(y), D.pad2, 1, true, P.Xdag, nullptr, D.interior,
+                        P.id, nullptr, done, st)))
+        return e;
+    HopArgs<S> cg;
+    memset(&cg, 0, sizeof(cg));
+    cg.cg_r = rho;
+    cg.cg_x = z;
+    cg.cg_p = pc;
+    cg.cg_alpha = sc.a;
+    cg.cg_first = it == 0 ? 1 : 0;
+    const CField<S> yc = cfield(y);
+    Field<S> none;
+    memset(&none, 0, sizeof(none));
+    return dom_hop<S>(c, none, D.interior, cfield(v), D.pad1, 0, true, scaled(P.Bdag, -0.25, -0.25),
+                      &yc, D.pad2, P.M5dag, part, done, st, &cg);
+}
+
 static InnerScalars inner_scalars(mspcg_ctx* c) {
     InnerScalars s;
     const int n = c->dom.ndom;
@@ -394,8 +439,7 @@ static int precond_core(mspcg_ctx* c, int l, CField<F64> r, Field<F64> z, const 
     Field<S> rho = half_field<S>(c, pf + "rho", D.ndom * nd);
     Field<S> p = half_field<S>(c, pf + "p", D.ndom * nd);
     Field<S> zz = half_field<S>(c, pf + "z", D.ndom * nd);
-    Field<S> w = half_field<S>(c, pf + "w", D.ndom * nd);
-    if (!rho.data || !p.data || !zz.data || !w.data) return MSPCG_ENOMEM;
+    if (!rho.data || !p.data || !zz.data) return MSPCG_ENOMEM;
     InnerScalars sc = inner_scalars(c);
     const long hop_np = hop_grid_x<S>(D.pad2.Vh, Ls);
     const int spb = kThreads / Ls;
@@ -421,26 +465,19 @@ static int precond_core(mspcg_ctx* c, int l, CField<F64> r, Field<F64> z, const 
                            (int)start_np, done);
         if (last_error()) return MSPCG_EHIP;
     }
+    // partials of the fused update: one per workgroup of the interior hop
+    const long upd_np = hop_grid_x<S>(D.interior.Vh, Ls);
     for (int it = 0; it < l; ++it) {
-        if ((e = block_A<S>(c, w, cfield(p), part, done, st))) return e;
-        Timed t(c, MSPCG_KC_BLAS, (double)D.ndom * nd * S::bytes_spinor * (it ? 9 : 8), st);
-        hipLaunchKernelGGL(inner_alpha, dim3(D.ndom), dim3(kThreads), 0, st, sc, part, (int)hop_np,
-                           done);
-        hipLaunchKernelGGL(inner_update_kernel<S>, dim3((unsigned)vec_np, D.ndom), dim3(kThreads),
-                           0, st, zz, rho, cfield(p), cfield(w), nd, sc, it == 0 ? 1 : 0, part,
-                           done);
+        if ((e = block_cg_step<S>(c, p, rho, zz, sc, it, part, hop_np, done, st))) return e;
         if (it + 1 < l) {
             hipLaunchKernelGGL(inner_beta, dim3(D.ndom), dim3(kThreads), 0, st, sc, part,
-                               (int)vec_np, done);
-            hipLaunchKernelGGL(inner_xpay_kernel<S>, dim3((unsigned)vec_np, D.ndom), dim3(kThreads),
-                               0, st, p, cfield(rho), nd, sc, done);
+                               (int)upd_np, done);
+            if (last_error()) return MSPCG_EHIP;
         }
-        if (last_error()) return MSPCG_EHIP;
     }
     Timed t(c, MSPCG_KC_BLAS, (double)D.ndom * nd * (192.0 + S::bytes_spinor), st);
     if (l == 0) {
-        MSPCG_HIP(hipMemsetAsync(z.data, 0, (size_t)12 * c->Nh * sizeof(double2), st));
-        return 0;
+        return launch_zero(z.data, c->Nh, st) ? MSPCG_EHIP : 0;
     }
     if (launch_domain_to_global<S, F64>(cfield(zz), z, c->L, D.blk, D.nb, Ls, 0, st))
         return MSPCG_EHIP;

@@ -19,9 +19,9 @@ OK, EINVAL, ENOMEM, EHIP, ENOGAUGE, ENOCONV, EBREAKDOWN, EUNSUPPORTED = 0, -1, -
 OP_D, OP_DDAG, OP_HOP, OP_HOPDAG, OP_MHAT, OP_MHATDAG, OP_A, OP_M5INV, OP_PREPARE, OP_KBLOCK = range(10)
 FP64, FP32, FP16 = 0, 1, 2
 SOLVER_CG, SOLVER_MIXED_CG, SOLVER_MSPCG = 0, 1, 2
-KC_HOP64, KC_HOP32, KC_HOPDOM, KC_FIVED, KC_BLAS, KC_HOPCG = range(6)
-KC_NAMES = ("hop64", "hop32", "hopdom", "fived", "blas", "hopcg")
-KC_COUNT = 6
+KC_HOP64, KC_HOP32, KC_HOPDOM, KC_FIVED, KC_BLAS, KC_HOPCG, KC_HOPDOMCG = range(7)
+KC_NAMES = ("hop64", "hop32", "hopdom", "fived", "blas", "hopcg", "hopdomcg")
+KC_COUNT = 7
 EXPORTS = ("mspcg_create", "mspcg_destroy", "mspcg_strerror", "mspcg_version",
            "mspcg_load_gauge", "mspcg_apply", "mspcg_set_blocking", "mspcg_precond",
            "mspcg_solve", "mspcg_solve_batch", "mspcg_force", "mspcg_get_tuning",
