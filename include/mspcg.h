@@ -225,8 +225,9 @@ int mspcg_autotune(mspcg_ctx* ctx, const mspcg_blocking* blocking, const char* c
                    hipStream_t stream);
 
 /* Block-shape autotuner for MSPCG (the blocks play the role of the paper's
- * nodes, Sec. 3): for each candidate blocking (halving the longest directions,
- * or quartering long ones), runs probe_iters outer iterations of MSPCG with
+ * nodes, Sec. 3): for each candidate blocking (halving any non-empty set of
+ * directions, or quartering long ones, where the padded domain still fits),
+ * runs probe_iters outer iterations of MSPCG with
  * base's local-solve settings on a fixed synthetic right-hand side and keeps
  * the blocking with the fastest residual reduction per second.  The choice
  * becomes the context's blocking and is returned in chosen (may be NULL). */

@@ -201,19 +201,13 @@ __global__ void fill_hash_kernel(double* p, long n, unsigned long long seed) {
 std::vector<mspcg_blocking> block_candidates(const mspcg_ctx* c, int pad) {
     std::vector<mspcg_blocking> v;
     auto ok = [&](int L, int b) { return b >= 2 && !(b & 1) && L % b == 0 && (L == b || L - b >= 2 * pad); };
-    // halve the k longest directions (k = 1..4), and quarter every direction when possible
-    int order[4] = {0, 1, 2, 3};
-    for (int i = 0; i < 4; ++i)
-        for (int j = i + 1; j < 4; ++j)
-            if (c->L[order[j]] > c->L[order[i]]) std::swap(order[i], order[j]);
-    for (int k = 1; k <= 4; ++k) {
+    // every non-empty set of halved directions, then a quarter in every direction
+    for (int mask = 1; mask < 16; ++mask) {
         mspcg_blocking b;
         b.pad = pad;
         bool good = true;
-        for (int m = 0; m < 4; ++m) b.block[m] = c->L[m];
-        for (int i = 0; i < k; ++i) {
-            const int m = order[i];
-            b.block[m] = c->L[m] / 2;
+        for (int m = 0; m < 4; ++m) {
+            b.block[m] = (mask >> m) & 1 ? c->L[m] / 2 : c->L[m];
             good = good && ok(c->L[m], b.block[m]);
         }
         if (good) v.push_back(b);
