@@ -1,6 +1,9 @@
-// Fifth-dimension-only kernel, FP64 BLAS-1 with fused reductions, per-domain
-// (block) CG vector updates for the sloppy inner solve, and the fixed-order
-// reductions that make every result bitwise reproducible (no float atomics).
+// Fifth-dimension-only kernel (optionally with the fused search-direction
+// update p = src + beta p), the CG scalar kernels, the remaining FP64 BLAS-1
+// passes with fused reductions (residual set-up, flexible-PCG dots, reliable
+// updates), and the fixed-order reductions that make every result bitwise
+// reproducible (no float atomics).  The per-iteration CG vector updates ride
+// on the operator kernels (cg_step, block_cg_step).
 #include "common.h"
 #include "fived.h"
 #include "kernels.h"
@@ -163,41 +166,6 @@ __global__ void cg_beta_kernel(DevScalars* sc, const double* partials, int npart
     }
 }
 
-// x += alpha p ; r -= alpha q ; partial |r|^2.  Flat over 12*N complex.
-__global__ void cg_update_xr_kernel(double2* x, double2* r, const double2* p, const double2* q,
-                                    long n, const DevScalars* sc, double* partials) {
-    if (sc->done) return;
-    const double al = sc->alpha;
-    double acc = 0;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long)gridDim.x * blockDim.x) {
-        const double2 pv = p[i], qv = q[i];
-        double2 xv = x[i], rv = r[i];
-        xv.x += al * pv.x;
-        xv.y += al * pv.y;
-        rv.x -= al * qv.x;
-        rv.y -= al * qv.y;
-        x[i] = xv;
-        r[i] = rv;
-        acc += rv.x * rv.x + rv.y * rv.y;
-    }
-    block_reduce_store(acc, partials + blockIdx.x);
-}
-
-// which = 0: p = r + beta p ; which = 1: p = r + (zr/zr_old) p handled by caller via beta
-__global__ void xpay_kernel(double2* p, const double2* r, long n, const DevScalars* sc) {
-    if (sc->done) return;
-    const double b = sc->beta;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long)gridDim.x * blockDim.x) {
-        const double2 rv = r[i];
-        double2 pv = p[i];
-        pv.x = rv.x + b * pv.x;
-        pv.y = rv.y + b * pv.y;
-        p[i] = pv;
-    }
-}
-
 __global__ void sub_norm_kernel(double2* r, const double2* b, const double2* ax, long n,
                                 double* partials) {
     double acc = 0;
@@ -237,51 +205,6 @@ __global__ void dot2_kernel(const double2* z, const double2* r, const double2* q
     block_reduce_store(b, partials + nparts + blockIdx.x);
 }
 
-__global__ void axpy_kernel(double2* y, const double2* x, double a, long n) {
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long)gridDim.x * blockDim.x) {
-        const double2 xv = x[i];
-        double2 yv = y[i];
-        yv.x += a * xv.x;
-        yv.y += a * xv.y;
-        y[i] = yv;
-    }
-}
-
-// FP32 variants of the CG vector updates (double accumulation of norms)
-__global__ void cg_update_xr32_kernel(float2* x, float2* r, const float2* p, const float2* q,
-                                      long n, const DevScalars* sc, double* partials) {
-    if (sc->done) return;
-    const float al = (float)sc->alpha;
-    double acc = 0;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long)gridDim.x * blockDim.x) {
-        const float2 pv = p[i], qv = q[i];
-        float2 xv = x[i], rv = r[i];
-        xv.x += al * pv.x;
-        xv.y += al * pv.y;
-        rv.x -= al * qv.x;
-        rv.y -= al * qv.y;
-        x[i] = xv;
-        r[i] = rv;
-        acc += (double)rv.x * rv.x + (double)rv.y * rv.y;
-    }
-    block_reduce_store(acc, partials + blockIdx.x);
-}
-
-__global__ void xpay32_kernel(float2* p, const float2* r, long n, const DevScalars* sc) {
-    if (sc->done) return;
-    const float b = (float)sc->beta;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long)gridDim.x * blockDim.x) {
-        const float2 rv = r[i];
-        float2 pv = p[i];
-        pv.x = rv.x + b * pv.x;
-        pv.y = rv.y + b * pv.y;
-        p[i] = pv;
-    }
-}
-
 // x (FP64) += xs (FP32); xs = 0.  Both are site-blocked with 16-byte chunks,
 // so FP64 element (site, c, s) at (site*12 + c)*Ls + s pairs with FP32
 // element (site*6 + c/2)*2*Ls + 2*s + c%2.
@@ -316,19 +239,6 @@ int last_error() { return hipGetLastError() == hipSuccess ? 0 : -2; }
 int launch_zero(double2* y, long N, hipStream_t st) {
     hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blas_grid_x(12 * N)), dim3(kThreads), 0, st, y,
                        12 * N);
-    return last_error();
-}
-
-int launch_cg_update_xr32(float2* x, float2* r, const float2* p, const float2* q, long N,
-                          const DevScalars* sc, double* partials, long nparts, hipStream_t st) {
-    hipLaunchKernelGGL(cg_update_xr32_kernel, dim3((unsigned)nparts), dim3(kThreads), 0, st, x, r,
-                       p, q, 12 * N, sc, partials);
-    return last_error();
-}
-
-int launch_xpay32(float2* p, const float2* r, long N, const DevScalars* sc, hipStream_t st) {
-    hipLaunchKernelGGL(xpay32_kernel, dim3((unsigned)blas_grid_x(12 * N)), dim3(kThreads), 0, st,
-                       p, r, 12 * N, sc);
     return last_error();
 }
 
@@ -395,20 +305,6 @@ int launch_cg_beta(DevScalars* sc, const double* partials, int nparts, double* h
     return last_error();
 }
 
-int launch_cg_update_xr(double2* x, double2* r, const double2* p, const double2* q, long N,
-                        const DevScalars* sc, double* partials, long nparts, hipStream_t st) {
-    hipLaunchKernelGGL(cg_update_xr_kernel, dim3((unsigned)nparts), dim3(kThreads), 0, st, x, r, p,
-                       q, 12 * N, sc, partials);
-    return last_error();
-}
-
-int launch_xpay(double2* p, const double2* r, long N, const DevScalars* sc, int,
-                hipStream_t st) {
-    hipLaunchKernelGGL(xpay_kernel, dim3((unsigned)blas_grid_x(12 * N)), dim3(kThreads), 0, st, p,
-                       r, 12 * N, sc);
-    return last_error();
-}
-
 int launch_sub_norm(double2* r, const double2* b, const double2* ax, long N, double* partials,
                     long nparts, hipStream_t st) {
     hipLaunchKernelGGL(sub_norm_kernel, dim3((unsigned)nparts), dim3(kThreads), 0, st, r, b, ax,
@@ -427,12 +323,6 @@ int launch_dot2(const double2* z, const double2* r, const double2* q, long N, do
                 long nparts, hipStream_t st) {
     hipLaunchKernelGGL(dot2_kernel, dim3((unsigned)nparts), dim3(kThreads), 0, st, z, r, q, 12 * N,
                        partials, nparts);
-    return last_error();
-}
-
-int launch_axpy(double2* y, const double2* x, double a, long N, hipStream_t st) {
-    hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)blas_grid_x(12 * N)), dim3(kThreads), 0, st, y,
-                       x, a, 12 * N);
     return last_error();
 }
 

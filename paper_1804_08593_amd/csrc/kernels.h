@@ -135,23 +135,15 @@ int launch_cg_beta(DevScalars* sc, const double* partials, int nparts, double* h
                    int hist_cap, hipStream_t st);
 
 // FP64 whole-lattice vector kernels
-int launch_cg_update_xr(double2* x, double2* r, const double2* p, const double2* q, long N,
-                        const DevScalars* sc, double* partials, long nparts, hipStream_t st);
-int launch_xpay(double2* p, const double2* r, long N, const DevScalars* sc, int which,
-                hipStream_t st);
 int launch_sub_norm(double2* r, const double2* b, const double2* ax, long N, double* partials,
                     long nparts, hipStream_t st);
 int launch_copy_norm(double2* dst, const double2* src, long N, double* partials, long nparts,
                      hipStream_t st);
 int launch_dot2(const double2* z, const double2* r, const double2* q, long N, double* partials,
                 long nparts, hipStream_t st);
-int launch_axpy(double2* y, const double2* x, double a, long N, hipStream_t st);
 int launch_zero(double2* y, long N, hipStream_t st);
 
 // FP32 iterations of the mixed-precision CG
-int launch_cg_update_xr32(float2* x, float2* r, const float2* p, const float2* q, long N,
-                          const DevScalars* sc, double* partials, long nparts, hipStream_t st);
-int launch_xpay32(float2* p, const float2* r, long N, const DevScalars* sc, hipStream_t st);
 int launch_accum32(double2* x, float2* xs, long N, int Ls, hipStream_t st);
 
 // Mixed-precision conversions (whole vectors)
