@@ -4,7 +4,8 @@ times (production tuning: XCD remap and traversal tiles).
 24^3x48, Ls=16: D and D^+ against the oracle on the whole lattice, A against
 the oracle's normal operator, and the bench's MSPCG / CG solves with their
 true residual re-measured by the oracle.  16^4x12: mixed-precision vs FP64 CG.
-32^3x64, Ls=12: MSPCG to 1e-10 with the hop checked on sampled sites."""
+32^3x64, Ls=12: the hop on sampled sites, and MSPCG to 1e-10 with 16 and with 128
+blocks."""
 import numpy as np
 import pytest
 import torch
@@ -87,26 +88,40 @@ def test_c2_mixed_precision_vs_fp64_cg():
     assert relerr(host(x32), host(x64)) <= 1e-7
 
 
-def test_c5b_mspcg_32c64():
+@pytest.fixture(scope="module")
+def c5b():
     dims, Ls = (32, 32, 32, 64), 12
     say("generating 32^3x64 x 12 inputs")
     act, U, ctx = setup(dims, Ls, 1.8, 0.01, 1.5, 0.5, eps=0.2, gseed=1006)
     b = synth.fermion_field(dims, Ls, 2006)
+    return act, U, ctx, b
+
+
+def test_c5b_hop_sampled_sites(c5b):
+    act, U, ctx, b = c5b
     bd = dev(b)
-    # the hop on sampled output sites of the full lattice
     out = torch.zeros_like(bd)
     ctx.apply(mspcg.OP_HOP, bd, out)
     rng = np.random.default_rng(5)
     sites = np.sort(rng.choice(act.V4, size=2000, replace=False))
     ref = O.hop_sites(act, U, b, sites)
-    got = host(out).reshape(Ls, act.V4, 4, 3)[:, sites]
-    assert relerr(got, ref) <= 1e-13
-    del out
+    got = host(out).reshape(act.Ls, act.V4, 4, 3)[:, sites]
+    err = relerr(got, ref)
+    say(f"  32^3x64 hop on 2000 sampled sites: relerr {err:.2e}")
+    assert err <= 1e-13
+
+
+# 16 blocks of 16^3x32, and 128 blocks of 8x8x16x16 (one per node of the
+# 128-node run of Sec. 3)
+@pytest.mark.parametrize("block", [(16, 16, 16, 32), (8, 8, 16, 16)])
+def test_c5b_mspcg_32c64(c5b, block):
+    act, U, ctx, b = c5b
+    bd = dev(b)
     x = torch.zeros_like(bd)
     st = ctx.solve(bd, x, mspcg.make_params(tol=1e-10, solver=mspcg.SOLVER_MSPCG,
-                                            block=(16, 16, 16, 32), pad=2, inner_iters=6,
+                                            block=block, pad=2, inner_iters=6,
                                             inner_prec=mspcg.FP16))
-    say(f"  32^3x64 MSPCG: {st['outer_iters']} it, {st['seconds']:.2f} s, "
+    say(f"  32^3x64 MSPCG blocks {block}: {st['outer_iters']} it, {st['seconds']:.2f} s, "
         f"resid {st['true_rel_resid']:.2e}")
     assert st["converged"] and st["true_rel_resid"] <= 1e-10
     dx = torch.zeros_like(bd)
