@@ -125,8 +125,8 @@ def main():
                     help="only run 5 plain 1 GiB device copies (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU sharding of "
-                                   "the blocks is described in DESIGN.md but not built"}))
+        print(json.dumps({"error": "bench.py runs on one GPU only; sharding the MSPCG blocks "
+                                   "over several GPUs is not implemented"}))
         sys.exit(2)
 
     import torch
