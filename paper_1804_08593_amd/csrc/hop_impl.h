@@ -233,7 +233,10 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
     using T = typename S::real;
     using E = typename S::elem;
     constexpr int SPB = 256 / LS;
-    constexpr int SITE_STRIDE = LS * 12 + 1;  // LDS row padding against bank conflicts
+    // s-exchange array, component-major with a padded row per (site, component):
+    // entry (site, s, c) at (site * 12 + c) * LSP + s, so the lanes of a site
+    // (consecutive s) and the chain threads (consecutive c) both hit distinct banks
+    constexpr int LSP = LS + 1;
     // FP16 links are decoded to FP32 once, when staged; LE is the LDS entry
     using LE = typename std::conditional<S::has_scale, nt_f2, E>::type;
     constexpr int NCH = 72 * (int)sizeof(E) / 16;   // 16-byte chunks of one site's links
@@ -241,7 +244,7 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
     constexpr bool LDSL = SPB * LSTR * 16 <= 40 * 1024;
     // the s-exchange array serves both the chain programs (EPH/EPA) and the
     // single-step programs applied by neighbour exchange
-    constexpr int EPI_BYTES = SPB * SITE_STRIDE * (int)sizeof(cx<T>);
+    constexpr int EPI_BYTES = SPB * 12 * LSP * (int)sizeof(cx<T>);
     constexpr int LNK_BYTES = LDSL ? SPB * LSTR * 16 : 16;
     constexpr int LDS_BYTES = EPI_BYTES > LNK_BYTES ? EPI_BYTES : LNK_BYTES;
     __shared__ __attribute__((aligned(16))) unsigned char smem[LDS_BYTES];
@@ -371,7 +374,7 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
         __syncthreads();  // LDS free: staged links or an earlier phase
         if (active) {
 #pragma unroll
-            for (int c = 0; c < 12; ++c) lds[sl * SITE_STRIDE + s * 12 + c] = v[c];
+            for (int c = 0; c < 12; ++c) lds[(sl * 12 + c) * LSP + s] = v[c];
         }
         __syncthreads();
         if (active) {
@@ -382,7 +385,7 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
                 const bool below = up != (P.dag[0] != 0);
                 const bool corner = below ? s == 0 : s == LS - 1;
                 const int s2 = below ? (corner ? LS - 1 : s - 1) : (corner ? 0 : s + 1);
-                const cx<T> nb = lds[sl * SITE_STRIDE + s2 * 12 + c];
+                const cx<T> nb = lds[(sl * 12 + c) * LSP + s2];
                 const T f = corner ? -(av * mf) : av;
                 const T sc = (T)(up ? P.scale[0] : P.scale[1]);
                 v[c] = {sc * (v[c].re + f * nb.re), sc * (v[c].im + f * nb.im)};
@@ -395,10 +398,10 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
             const int csl = ch / 12, comp = ch - csl * 12;
             cx<T> v[LS];
 #pragma unroll
-            for (int t = 0; t < LS; ++t) v[t] = lds[csl * SITE_STRIDE + t * 12 + comp];
+            for (int t = 0; t < LS; ++t) v[t] = lds[(csl * 12 + comp) * LSP + t];
             apply_prog<LS, T>(P, comp < 6, mf, v);
 #pragma unroll
-            for (int t = 0; t < LS; ++t) lds[csl * SITE_STRIDE + t * 12 + comp] = v[t];
+            for (int t = 0; t < LS; ++t) lds[(csl * 12 + comp) * LSP + t] = v[t];
         }
     };
 
@@ -417,13 +420,13 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
         __syncthreads();  // every wave is done with the staged links
         if (active) {
 #pragma unroll
-            for (int c = 0; c < 12; ++c) lds[sl * SITE_STRIDE + s * 12 + c] = acc[c];
+            for (int c = 0; c < 12; ++c) lds[(sl * 12 + c) * LSP + s] = acc[c];
         }
         __syncthreads();
         chains(a.ph);
         __syncthreads();
 #pragma unroll
-        for (int c = 0; c < 12; ++c) res[c] = lds[sl * SITE_STRIDE + s * 12 + c];
+        for (int c = 0; c < 12; ++c) res[c] = lds[(sl * 12 + c) * LSP + s];
     }
 
     if (a.has_aux) {
@@ -459,14 +462,14 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
             __syncthreads();  // the hop epilogue may still read lds
             if (active) {
 #pragma unroll
-                for (int c = 0; c < 12; ++c) lds[sl * SITE_STRIDE + s * 12 + c] = x[c];
+                for (int c = 0; c < 12; ++c) lds[(sl * 12 + c) * LSP + s] = x[c];
             }
             __syncthreads();
             chains(a.pa);
             __syncthreads();
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                const cx<T> t = lds[sl * SITE_STRIDE + s * 12 + c];
+                const cx<T> t = lds[(sl * 12 + c) * LSP + s];
                 res[c].re += t.re;
                 res[c].im += t.im;
             }
