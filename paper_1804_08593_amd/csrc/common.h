@@ -39,11 +39,16 @@ template <typename T>
 __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
     return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
-// a += b * c
+// fused a*b + c in the arithmetic type (one rounding)
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// a += b * c as a chain of four fused multiply-adds
 template <typename T>
 __device__ __forceinline__ void cfma(cx<T>& a, cx<T> b, cx<T> c) {
-    a.re += b.re * c.re - b.im * c.im;
-    a.im += b.re * c.im + b.im * c.re;
+    a.re = fmadd(b.re, c.re, a.re);
+    a.re = fmadd(-b.im, c.im, a.re);
+    a.im = fmadd(b.re, c.im, a.im);
+    a.im = fmadd(b.im, c.re, a.im);
 }
 
 // Storage policies.  `real` is the arithmetic type; `elem` the stored complex.
@@ -136,14 +141,16 @@ __device__ __forceinline__ void load_raw_at(CField<S> f, long base, int s, int l
 }
 
 template <class S>
-__device__ __forceinline__ void decode_raw(const RawSpinor<S>& r, cx<typename S::real> (&v)[12]) {
+__device__ __forceinline__ void decode_raw(const RawSpinor<S>& r, cx<typename S::real> (&v)[12],
+                                           bool apply_scale = true) {
     if constexpr (S::has_scale) {
+        const float sc = apply_scale ? r.sc : 1.f;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            v[4 * k + 0] = h2f(r.c[k].x, r.sc);
-            v[4 * k + 1] = h2f(r.c[k].y, r.sc);
-            v[4 * k + 2] = h2f(r.c[k].z, r.sc);
-            v[4 * k + 3] = h2f(r.c[k].w, r.sc);
+            v[4 * k + 0] = h2f(r.c[k].x, sc);
+            v[4 * k + 1] = h2f(r.c[k].y, sc);
+            v[4 * k + 2] = h2f(r.c[k].z, sc);
+            v[4 * k + 3] = h2f(r.c[k].w, sc);
         }
     } else if constexpr (sizeof(typename S::real) == 8) {
 #pragma unroll

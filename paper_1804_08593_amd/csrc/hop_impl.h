@@ -64,36 +64,38 @@ __device__ __forceinline__ void project(const cx<T> (&p)[12], cx<T> (&h)[6]) {
     }
 }
 
-// acc_up += w ; acc_dn += sig e_mu^+ w
-template <int MU, int SIG, typename T>
-__device__ __forceinline__ void reconstruct(const cx<T> (&w)[6], cx<T> (&acc)[12]) {
+// acc_up += k w ; acc_dn += sig k e_mu^+ w, with k = 1 or, for FP16 storage,
+// the neighbour's per-(x,s) scale (then every update is one fused multiply-add)
+template <int MU, int SIG, bool SC, typename T>
+__device__ __forceinline__ void reconstruct(const cx<T> (&w)[6], cx<T> (&acc)[12], T k) {
+    auto add = [&](T& a, T x) { a = SC ? fmadd(k, x, a) : a + x; };
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const cx<T> w0 = w[c], w1 = w[3 + c];
-        acc[c].re += w0.re;
-        acc[c].im += w0.im;
-        acc[3 + c].re += w1.re;
-        acc[3 + c].im += w1.im;
+        add(acc[c].re, w0.re);
+        add(acc[c].im, w0.im);
+        add(acc[3 + c].re, w1.re);
+        add(acc[3 + c].im, w1.im);
         if constexpr (MU == 0) {  // e^+ w = (i w1, i w0)
-            acc[6 + c].re -= SIG * w1.im;
-            acc[6 + c].im += SIG * w1.re;
-            acc[9 + c].re -= SIG * w0.im;
-            acc[9 + c].im += SIG * w0.re;
+            add(acc[6 + c].re, -SIG * w1.im);
+            add(acc[6 + c].im, SIG * w1.re);
+            add(acc[9 + c].re, -SIG * w0.im);
+            add(acc[9 + c].im, SIG * w0.re);
         } else if constexpr (MU == 1) {  // e^+ w = (w1, -w0)
-            acc[6 + c].re += SIG * w1.re;
-            acc[6 + c].im += SIG * w1.im;
-            acc[9 + c].re -= SIG * w0.re;
-            acc[9 + c].im -= SIG * w0.im;
+            add(acc[6 + c].re, SIG * w1.re);
+            add(acc[6 + c].im, SIG * w1.im);
+            add(acc[9 + c].re, -SIG * w0.re);
+            add(acc[9 + c].im, -SIG * w0.im);
         } else if constexpr (MU == 2) {  // e^+ w = (i w0, -i w1)
-            acc[6 + c].re -= SIG * w0.im;
-            acc[6 + c].im += SIG * w0.re;
-            acc[9 + c].re += SIG * w1.im;
-            acc[9 + c].im -= SIG * w1.re;
+            add(acc[6 + c].re, -SIG * w0.im);
+            add(acc[6 + c].im, SIG * w0.re);
+            add(acc[9 + c].re, SIG * w1.im);
+            add(acc[9 + c].im, -SIG * w1.re);
         } else {  // e^+ w = w
-            acc[6 + c].re += SIG * w0.re;
-            acc[6 + c].im += SIG * w0.im;
-            acc[9 + c].re += SIG * w1.re;
-            acc[9 + c].im += SIG * w1.im;
+            add(acc[6 + c].re, SIG * w0.re);
+            add(acc[6 + c].im, SIG * w0.im);
+            add(acc[9 + c].re, SIG * w1.re);
+            add(acc[9 + c].im, SIG * w1.im);
         }
     }
 }
@@ -108,11 +110,13 @@ __device__ __forceinline__ cx<typename S::real> elem_cx(typename S::elem e) {
     }
 }
 
-// acc += (1 + SIG g_mu) U p   (u: the 3x3 link, row-major)
+// acc += k (1 + SIG g_mu) U p   (u: the 3x3 link, row-major; k = 1 unless the
+// storage carries a scale, which then multiplies the projected product)
 template <class S, int MU, int SIG>
 __device__ __forceinline__ void dir_apply(const cx<typename S::real> (&p)[12],
                                           const cx<typename S::real> (&u)[9],
-                                          cx<typename S::real> (&acc)[12]) {
+                                          cx<typename S::real> (&acc)[12],
+                                          typename S::real k) {
     using T = typename S::real;
     cx<T> h[6];
     project<MU, SIG>(p, h);
@@ -126,7 +130,7 @@ __device__ __forceinline__ void dir_apply(const cx<typename S::real> (&p)[12],
             cfma(t, u[i * 3 + 2], h[sp * 3 + 2]);
             w[sp * 3 + i] = t;
         }
-    reconstruct<MU, SIG>(w, acc);
+    reconstruct<MU, SIG, S::has_scale>(w, acc, k);
 }
 
 // Input-box position of one output site, set up once per thread so that each
@@ -350,7 +354,7 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
                 constexpr int LD = (FWD ? MU : 4 + MU) * 9;  // first entry of this link
                 if (ok[j]) {
                     cx<T> p[12];
-                    decode_raw<S>(raw[j], p);
+                    decode_raw<S>(raw[j], p, false);
                     cx<T> u[9];
                     if constexpr (LDSL) {
                         const LE* le = reinterpret_cast<const LE*>(lnk + sl * LSTR) + LD;
@@ -360,7 +364,7 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
 #pragma unroll
                         for (int k = 0; k < 9; ++k) u[k] = load_link<S, MSPCG_HOP_NT>(gl + LD + k);
                     }
-                    dir_apply<S, MU, FWD ? SF : SB>(p, u, acc);
+                    dir_apply<S, MU, FWD ? SF : SB>(p, u, acc, S::has_scale ? (T)raw[j].sc : (T)1);
                 }
             });
         });
