@@ -42,24 +42,28 @@
 
 namespace mspcg {
 
-// h = psi_up + sig e_mu psi_dn   (components: spin*3 + colour)
-template <int MU, int SIG, typename T>
-__device__ __forceinline__ void project(const cx<T> (&p)[12], cx<T> (&h)[6]) {
+// h = psi_up + sig e_mu psi_dn   (components: spin*3 + colour).  With MIX the
+// inputs are decoded FP16 values and each sum is formed as a fused
+// multiply-add with an opaque unit factor, which the compiler turns into one
+// mixed-precision instruction reading both FP16 halves (exact sum, one rounding).
+template <int MU, int SIG, bool MIX, typename T>
+__device__ __forceinline__ void project(const cx<T> (&p)[12], cx<T> (&h)[6], T one) {
+    auto pm = [&](T u, T d) { return MIX ? fmadd(d, one, u) : u + d; };
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const cx<T> u0 = p[c], u1 = p[3 + c], d0 = p[6 + c], d1 = p[9 + c];
         if constexpr (MU == 0) {  // e d = (-i d1, -i d0)
-            h[c] = {u0.re + SIG * d1.im, u0.im - SIG * d1.re};
-            h[3 + c] = {u1.re + SIG * d0.im, u1.im - SIG * d0.re};
+            h[c] = {pm(u0.re, SIG * d1.im), pm(u0.im, -SIG * d1.re)};
+            h[3 + c] = {pm(u1.re, SIG * d0.im), pm(u1.im, -SIG * d0.re)};
         } else if constexpr (MU == 1) {  // e d = (-d1, d0)
-            h[c] = {u0.re - SIG * d1.re, u0.im - SIG * d1.im};
-            h[3 + c] = {u1.re + SIG * d0.re, u1.im + SIG * d0.im};
+            h[c] = {pm(u0.re, -SIG * d1.re), pm(u0.im, -SIG * d1.im)};
+            h[3 + c] = {pm(u1.re, SIG * d0.re), pm(u1.im, SIG * d0.im)};
         } else if constexpr (MU == 2) {  // e d = (-i d0, i d1)
-            h[c] = {u0.re + SIG * d0.im, u0.im - SIG * d0.re};
-            h[3 + c] = {u1.re - SIG * d1.im, u1.im + SIG * d1.re};
+            h[c] = {pm(u0.re, SIG * d0.im), pm(u0.im, -SIG * d0.re)};
+            h[3 + c] = {pm(u1.re, -SIG * d1.im), pm(u1.im, SIG * d1.re)};
         } else {  // e d = d
-            h[c] = {u0.re + SIG * d0.re, u0.im + SIG * d0.im};
-            h[3 + c] = {u1.re + SIG * d1.re, u1.im + SIG * d1.im};
+            h[c] = {pm(u0.re, SIG * d0.re), pm(u0.im, SIG * d0.im)};
+            h[3 + c] = {pm(u1.re, SIG * d1.re), pm(u1.im, SIG * d1.im)};
         }
     }
 }
@@ -116,10 +120,10 @@ template <class S, int MU, int SIG>
 __device__ __forceinline__ void dir_apply(const cx<typename S::real> (&p)[12],
                                           const cx<typename S::real> (&u)[9],
                                           cx<typename S::real> (&acc)[12],
-                                          typename S::real k) {
+                                          typename S::real k, typename S::real one) {
     using T = typename S::real;
     cx<T> h[6];
-    project<MU, SIG>(p, h);
+    project<MU, SIG, S::has_scale>(p, h, one);
     cx<T> w[6];
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp)
@@ -232,8 +236,16 @@ __device__ __forceinline__ void sfor(F&& f) {
 // staged in LDS with coalesced 16-byte loads (one load per 16 bytes of links
 // instead of one per element and lane) when they fit; the epilogue reuses
 // that LDS after the direction loop.
+// FP16-storage hops at Ls = 8 or 16 without an aux chain or fused CG update
+// fit in 80 VGPRs without spilling: ask for 6 waves per SIMD there (their
+// arithmetic, not memory, sets the pace)
+template <class S, int LS, bool EPA, bool CG>
+constexpr int hop_min_waves() {
+    return (S::has_scale && !EPA && !CG && (LS == 8 || LS == 16)) ? 6 : MSPCG_HOP_MINWAVES;
+}
+
 template <class S, int LS, bool DAG, bool EPH, bool EPA, bool CG = false>
-__global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S> a) {
+__global__ __launch_bounds__(256, (hop_min_waves<S, LS, EPA, CG>())) void hop_kernel(HopArgs<S> a) {
     using T = typename S::real;
     using E = typename S::elem;
     constexpr int SPB = 256 / LS;
@@ -328,6 +340,9 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
     if (active) {
         const long ibase = (long)d * g.in.Vh;
         const InPos ip = in_position(g, gc);
+        // 1.0 that the compiler cannot fold (see project)
+        T one = 1;
+        if constexpr (S::has_scale) asm("s_mov_b32 %0, 1.0" : "=s"(one));
         // forward terms use (1 - g) and backward (1 + g); the dagger swaps them
         constexpr int SF = DAG ? 1 : -1;
         constexpr int SB = -SF;
@@ -364,7 +379,7 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
 #pragma unroll
                         for (int k = 0; k < 9; ++k) u[k] = load_link<S, MSPCG_HOP_NT>(gl + LD + k);
                     }
-                    dir_apply<S, MU, FWD ? SF : SB>(p, u, acc, S::has_scale ? (T)raw[j].sc : (T)1);
+                    dir_apply<S, MU, FWD ? SF : SB>(p, u, acc, S::has_scale ? (T)raw[j].sc : (T)1, one);
                 }
             });
         });
@@ -488,12 +503,15 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
             const T al = (T)(a.cg_alpha ? a.cg_alpha[d] : a.cg_sc->alpha);
             cx<T> v[12];
             load_spinor_at<S>(cfield(a.cg_r), obase, s, LS, v);
+            T t2 = 0;  // one entry's 24 squares in the arithmetic type
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 v[c].re -= al * res[c].re;
                 v[c].im -= al * res[c].im;
-                n2 += (double)v[c].re * v[c].re + (double)v[c].im * v[c].im;
+                t2 = fmadd(v[c].re, v[c].re, t2);
+                t2 = fmadd(v[c].im, v[c].im, t2);
             }
+            n2 = (double)t2;
             store_spinor_at<S>(a.cg_r, obase, s, LS, v);
             cx<T> pv[12];
             load_spinor_at<S>(a.cg_p, obase, s, LS, pv);
@@ -519,8 +537,13 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void hop_kernel(HopArgs<S>
         if (active) {
             // norm of what was stored (FP16 rounding included is not needed:
             // the reduction uses the arithmetic value)
+            T t2 = 0;
 #pragma unroll
-            for (int c = 0; c < 12; ++c) n2 += (double)res[c].re * res[c].re + (double)res[c].im * res[c].im;
+            for (int c = 0; c < 12; ++c) {
+                t2 = fmadd(res[c].re, res[c].re, t2);
+                t2 = fmadd(res[c].im, res[c].im, t2);
+            }
+            n2 = (double)t2;
         }
         block_sum_store<S, LS>(n2, a.partials + (long)d * gridDim.x + bx);
     }
