@@ -68,11 +68,12 @@ __device__ __forceinline__ void project(const cx<T> (&p)[12], cx<T> (&h)[6], T o
     }
 }
 
-// acc_up += k w ; acc_dn += sig k e_mu^+ w, with k = 1 or, for FP16 storage,
-// the neighbour's per-(x,s) scale (then every update is one fused multiply-add)
-template <int MU, int SIG, bool SC, typename T>
+// acc_up += k w ; acc_dn += sig k e_mu^+ w with k the neighbour's FP16 scale
+// (1 for unscaled storage), each update one fused multiply-add; FIRST assigns
+// instead of adding.
+template <int MU, int SIG, bool FIRST, typename T>
 __device__ __forceinline__ void reconstruct(const cx<T> (&w)[6], cx<T> (&acc)[12], T k) {
-    auto add = [&](T& a, T x) { a = SC ? fmadd(k, x, a) : a + x; };
+    auto add = [&](T& a, T x) { a = FIRST ? k * x : fmadd(k, x, a); };
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const cx<T> w0 = w[c], w1 = w[3 + c];
@@ -114,9 +115,9 @@ __device__ __forceinline__ cx<typename S::real> elem_cx(typename S::elem e) {
     }
 }
 
-// acc += k (1 + SIG g_mu) U p   (u: the 3x3 link, row-major; k = 1 unless the
-// storage carries a scale, which then multiplies the projected product)
-template <class S, int MU, int SIG>
+// acc (+)= k (1 + SIG g_mu) U p   (u: the 3x3 link, row-major; k as in
+// reconstruct)
+template <class S, int MU, int SIG, bool FIRST>
 __device__ __forceinline__ void dir_apply(const cx<typename S::real> (&p)[12],
                                           const cx<typename S::real> (&u)[9],
                                           cx<typename S::real> (&acc)[12],
@@ -134,7 +135,17 @@ __device__ __forceinline__ void dir_apply(const cx<typename S::real> (&p)[12],
             cfma(t, u[i * 3 + 2], h[sp * 3 + 2]);
             w[sp * 3 + i] = t;
         }
-    reconstruct<MU, SIG, S::has_scale>(w, acc, k);
+    reconstruct<MU, SIG, FIRST>(w, acc, k);
+}
+
+// A global-memory pointer with the same value in every lane of the wave,
+// moved to scalar registers so that loads add a 32-bit lane offset to it.
+using gchar = const __attribute__((address_space(1))) char;
+__device__ __forceinline__ gchar* uniform_ptr(const char* p) {
+    const unsigned long v = reinterpret_cast<unsigned long>(p);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return reinterpret_cast<gchar*>(((unsigned long)hi << 32) | lo);
 }
 
 // Input-box position of one output site, set up once per thread so that each
@@ -334,12 +345,19 @@ __global__ __launch_bounds__(256, (hop_min_waves<S, LS, EPA, CG>())) void hop_ke
     }
     if constexpr (LDSL) __syncthreads();
 
+    constexpr int KC = Chunk<S>::K;
     cx<T> acc[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
     if (active) {
         const long ibase = (long)d * g.in.Vh;
         const InPos ip = in_position(g, gc);
+        // the domain's input box (a workgroup-uniform base, kept in scalar
+        // registers) and this lane's byte offsets from it
+        gchar* in_d = uniform_ptr(reinterpret_cast<const char*>(a.in.data) + ibase * LS * KC * 16);
+        gchar* sc_d =
+            S::has_scale ? uniform_ptr(reinterpret_cast<const char*>(a.in.scale + ibase * LS)) : nullptr;
+        const unsigned s16 = (unsigned)s * 16u, s4 = (unsigned)s * 4u;
         // 1.0 that the compiler cannot fold (see project)
         T one = 1;
         if constexpr (S::has_scale) asm("s_mov_b32 %0, 1.0" : "=s"(one));
@@ -360,7 +378,21 @@ __global__ __launch_bounds__(256, (hop_min_waves<S, LS, EPA, CG>())) void hop_ke
                 constexpr bool FWD = (D % 2) == 0;
                 long n = 0;
                 ok[j] = neighbour<MU, FWD ? 1 : 0>(g, ip, n);
-                if (ok[j]) load_raw_at<S>(a.in, (ibase + n) * LS, s, LS, raw[j]);
+                if (ok[j]) {
+                    if constexpr (S::has_scale) {
+                        const unsigned un = (unsigned)n;
+                        gchar* pb = in_d + (unsigned long)((unsigned)__umul24(un, LS * KC * 16) + s16);
+#pragma unroll
+                        for (int k = 0; k < KC; ++k)
+                            raw[j].c[k] = *reinterpret_cast<const __attribute__((address_space(1))) nt_u4*>(
+                                pb + k * LS * 16);
+                        if constexpr (S::has_scale)
+                            raw[j].sc = *reinterpret_cast<const __attribute__((address_space(1))) float*>(
+                                sc_d + (unsigned long)((unsigned)__umul24(un, LS * 4) + s4));
+                    } else {
+                        load_raw_at<S>(a.in, (ibase + n) * LS, s, LS, raw[j]);
+                    }
+                }
             });
             sfor<PF>([&](auto j) {
                 constexpr int D = G0 + decltype(j)::value;
@@ -379,7 +411,8 @@ __global__ __launch_bounds__(256, (hop_min_waves<S, LS, EPA, CG>())) void hop_ke
 #pragma unroll
                         for (int k = 0; k < 9; ++k) u[k] = load_link<S, MSPCG_HOP_NT>(gl + LD + k);
                     }
-                    dir_apply<S, MU, FWD ? SF : SB>(p, u, acc, S::has_scale ? (T)raw[j].sc : (T)1, one);
+                    const T k = S::has_scale ? (T)raw[j].sc : (T)1;
+                    dir_apply<S, MU, FWD ? SF : SB, false>(p, u, acc, k, one);
                 }
             });
         });
@@ -586,8 +619,13 @@ static void launch_ls(const HopArgs<S>& a, int ndom, bool dag, hipStream_t st) {
 }
 
 template <class S>
-int launch_hop(const HopArgs<S>& a, int Ls, int ndom, bool dag, hipStream_t st) {
-    if (a.cg_r.data && (!dag || !a.partials)) return -1;
+int launch_hop(const HopArgs<S>& a0, int Ls, int ndom, bool dag, hipStream_t st) {
+    if (a0.cg_r.data && (!dag || !a0.partials)) return -1;
+    HopArgs<S> a = a0;
+    const long site_bytes = (long)Ls * Chunk<S>::K * 16;
+    a.off32 = a.g.in.Vh < (1L << 24) && a.g.in.Vh * site_bytes <= 0xffffffffL;
+    // FP16-storage hops address neighbours with 32-bit offsets only
+    if (S::has_scale && !a.off32) return -1;
     switch (Ls) {
 #define MSPCG_CASE(L) \
     case L: launch_ls<S, L>(a, ndom, dag, st); break;

@@ -47,6 +47,10 @@ struct HopArgs {
     const double* cg_alpha;
     int cg_keep_out;
     int cg_first;
+    // set by launch_hop: one domain's input box spans < 4 GB and < 2^24 sites
+    // (required for FP16 storage, whose neighbour addresses are 32-bit offsets
+    // from the domain's base)
+    int off32;
 };
 
 template <class S>
