@@ -457,6 +457,8 @@ extern "C" void mspcg_destroy(mspcg_ctx* c) {
     if (c->partials) (void)hipFree(c->partials);
     if (c->hist) (void)hipFree(c->hist);
     if (c->dom.links) (void)hipFree(c->dom.links);
+    if (c->dom.list_y) (void)hipFree(c->dom.list_y);
+    if (c->dom.list_v) (void)hipFree(c->dom.list_v);
     (void)hipFree(c->sc);
     (void)hipHostFree(c->sc_host);
     for (auto e : c->evpool) (void)hipEventDestroy(e);

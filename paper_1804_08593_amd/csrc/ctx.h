@@ -50,6 +50,16 @@ struct Domains {
     bool built;
     int prec;      // precision of the links below
     void* links;   // [ndom][2][8][9][Vh(pad2)]
+    // Output sites of the middle hops of the block operator that matter:
+    // even sites of the pad2 box within Manhattan distance 2 of the block
+    // (where Mhat_D p can be nonzero) and odd sites of the pad1 box within
+    // distance 1 (the only ones the last hop reads).  Checkerboard indices
+    // of the box, ascending, shared by all domains; null when pad = 0.
+    // rd_*: sites of the hop's input box (one parity) that those outputs read.
+    int* list_y;
+    long n_y, rd_y;
+    int* list_v;
+    long n_v, rd_v;
 };
 
 }  // namespace mspcg

@@ -284,7 +284,7 @@ __global__ __launch_bounds__(256, (hop_min_waves<S, LS, EPA, CG>())) void hop_ke
     const int sl = threadIdx.x / LS;
     const int s = threadIdx.x - sl * LS;
     const long t_lin = (long)bx * SPB + sl;  // position in the traversal order
-    const bool active = sl < SPB && t_lin < a.g.out.Vh;
+    const bool active = sl < SPB && t_lin < (a.site_list ? a.n_list : a.g.out.Vh);
     const HopGeom& g = a.g;
     long cb = t_lin;
 
@@ -292,7 +292,10 @@ __global__ __launch_bounds__(256, (hop_min_waves<S, LS, EPA, CG>())) void hop_ke
     const E* gl = nullptr;
     if (active) {
         int oc[4];
-        if (a.tile[0]) {
+        if (a.site_list) {
+            cb = a.site_list[t_lin];
+            box_coords(g.out, cb, g.out_par, oc);
+        } else if (a.tile[0]) {
             // 4D-tiled traversal: consecutive workgroups sweep compact tiles of
             // extent tile[mu] (even, dividing the box), tiles in lex order
             Box tb;
@@ -585,7 +588,8 @@ __global__ __launch_bounds__(256, (hop_min_waves<S, LS, EPA, CG>())) void hop_ke
 template <class S, int LS>
 static void launch_ls(const HopArgs<S>& a, int ndom, bool dag, hipStream_t st) {
     constexpr int SPB = 256 / LS;
-    dim3 grid((unsigned)((a.g.out.Vh + SPB - 1) / SPB), (unsigned)ndom);
+    const long nout = a.site_list ? a.n_list : a.g.out.Vh;
+    dim3 grid((unsigned)((nout + SPB - 1) / SPB), (unsigned)ndom);
     dim3 block(SPB * LS);
     // programs of at most one bidiagonal step are applied by s-exchange
     auto chain = [](const FiveDProg& P) {

@@ -47,6 +47,11 @@ struct HopArgs {
     const double* cg_alpha;
     int cg_keep_out;
     int cg_first;
+    // optional: the output sites to compute, as checkerboard indices of the
+    // output box shared by every domain (n_list of them); the traversal tile
+    // is ignored then
+    const int* site_list;
+    long n_list;
     // set by launch_hop: one domain's input box spans < 4 GB and < 2^24 sites
     // (required for FP16 storage, whose neighbour addresses are 32-bit offsets
     // from the domain's base)
@@ -56,7 +61,7 @@ struct HopArgs {
 template <class S>
 int launch_hop(const HopArgs<S>& a, int Ls, int ndom, bool dag, hipStream_t st);
 template <class S>
-long hop_grid_x(long Vh, int Ls);
+long hop_grid_x(long Vh, int Ls);  // workgroups per domain for Vh output sites
 
 // out = P(in) on one box per domain (optionally |out|^2 partials).
 template <class S>

@@ -10,7 +10,10 @@
 // sites (the "domain") with every hop leaving the domain dropped.  Each stage
 // of Mhat_D^+ Mhat_D is evaluated only on the part of the domain that can
 // still contribute (odd sites within one site of the block, even sites
-// within two), i.e. the four hops run on boxes padded by 1, 2, 1 and 0.
+// within two): the four hops run on boxes padded by 1, 2, 1 and 0, and the
+// middle two only on the sites of their box within Manhattan distance 2 and
+// 1 of the block (the first hop fills its whole box, so the sites the second
+// reads beyond distance 1 hold exact zeros).
 // A block that spans a whole lattice direction wraps periodically there.
 // pad = 0 gives the cheaper Dirichlet-cut block operator Mhat_s^+ Mhat_s.
 //
@@ -18,6 +21,8 @@
 // in one launch per step, with per-block scalars; storage precision S (FP16
 // with per-(x,s) scales, FP32 or FP64), arithmetic in FP32 (FP64 for F64).
 #include <string.h>
+
+#include <vector>
 
 #include "ctx.h"
 #include "fived.h"
@@ -167,6 +172,55 @@ static Box dom_box(const mspcg_ctx* c, const Domains& D, int padk) {
     return b;
 }
 
+// Manhattan distance from the block of local site c of box b (directions the
+// block spans wrap and count zero).
+static int block_distance(const Domains& D, const Box& b, const int c[4]) {
+    int dist = 0;
+    for (int m = 0; m < 4; ++m) {
+        if (D.nb[m] == 1) continue;
+        const int x = c[m] + b.off[m];
+        dist += x < 0 ? -x : (x >= D.blk[m] ? x - D.blk[m] + 1 : 0);
+    }
+    return dist;
+}
+
+// Host mirror of the kernels' checkerboard enumeration of a box.
+static void host_box_coords(const Box& b, long cb, int par, int c[4]) {
+    const int hx = b.E[0] >> 1;
+    long r = cb / hx;
+    const int xh = (int)(cb - r * hx);
+    c[1] = (int)(r % b.E[1]);
+    r /= b.E[1];
+    c[2] = (int)(r % b.E[2]);
+    c[3] = (int)(r / b.E[2]);
+    const int so = b.off[0] + b.off[1] + b.off[2] + b.off[3];
+    c[0] = 2 * xh + ((par + c[1] + c[2] + c[3] + so) & 1);
+}
+
+// Sites of parity `par` in box b within Manhattan distance `q` of the block
+// (uploaded when `out` is given), and how many sites of the other parity
+// in box `in` lie within q + 1 (what a hop onto those sites reads).
+static int site_list(const Domains& D, const Box& b, int par, int q, const Box& in, int** out,
+                     long* n, long* nread) {
+    std::vector<int> v;
+    int c[4];
+    for (long cb = 0; cb < b.Vh; ++cb) {
+        host_box_coords(b, cb, par, c);
+        if (block_distance(D, b, c) <= q) v.push_back((int)cb);
+    }
+    long r = 0;
+    for (long cb = 0; cb < in.Vh; ++cb) {
+        host_box_coords(in, cb, par ^ 1, c);
+        if (block_distance(D, in, c) <= q + 1) ++r;
+    }
+    *n = (long)v.size();
+    *nread = r;
+    if (hipMalloc(out, v.size() * sizeof(int)) != hipSuccess) return MSPCG_ENOMEM;
+    if (hipMemcpy(*out, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+        return MSPCG_EHIP;
+    return 0;
+}
+
 template <class S>
 static size_t link_elems(const Domains& D) {
     return (size_t)D.ndom * 2 * 8 * 9 * D.pad2.Vh;
@@ -212,6 +266,14 @@ int domains_setup(mspcg_ctx* c, const mspcg_blocking& bk, int prec, hipStream_t 
         e = launch_pack_links<F16>(c->U, (__half2*)D.links, c->L, D.blk, D.nb, D.pad2,
                                    c->act.antiperiodic_t, st);
     if (e) return MSPCG_EHIP;
+    if (D.list_y) (void)hipFree(D.list_y);
+    if (D.list_v) (void)hipFree(D.list_v);
+    D.list_y = D.list_v = nullptr;
+    D.n_y = D.n_v = D.rd_y = D.rd_v = 0;
+    if (bk.pad > 0) {
+        if ((e = site_list(D, D.pad2, 0, 2, D.pad1, &D.list_y, &D.n_y, &D.rd_y))) return e;
+        if ((e = site_list(D, D.pad1, 1, 1, D.pad2, &D.list_v, &D.n_v, &D.rd_v))) return e;
+    }
     D.prec = prec;
     D.built = true;
     return 0;
@@ -253,7 +315,8 @@ template <class S>
 static int dom_hop(mspcg_ctx* c, Field<S> out, const Box& bout, CField<S> in, const Box& bin,
                    int out_par, bool dag, const FiveDProg& ph, const CField<S>* aux,
                    const Box& baux, const FiveDProg& pa, double* partials, const int* done,
-                   hipStream_t st, const HopArgs<S>* cg = nullptr) {
+                   hipStream_t st, const HopArgs<S>* cg = nullptr, const int* list = nullptr,
+                   long nlist = 0, long nread = 0) {
     const Domains& D = c->dom;
     HopArgs<S> a;
     memset(&a, 0, sizeof(a));
@@ -285,14 +348,18 @@ static int dom_hop(mspcg_ctx* c, Field<S> out, const Box& bout, CField<S> in, co
     a.done = done;
     a.xcd_remap = c->tune.xcd_remap;
     pick_tile(c->tune.tile[prec_index<S>()], bout, a.tile);
+    a.site_list = list;
+    a.n_list = nlist;
     // spinor entries per s moved (one parity): out, the input sites the hop
-    // reads, aux at the output sites; the fused update reads rho, p (z unless
-    // first) and writes rho, z in place of out
-    double entries = (double)bout.Vh + hop_read_sites(bin, bout) / 2 +
+    // reads, aux at the output sites (aux boxes lie inside the listed region);
+    // the fused update reads rho, p (z unless first) and writes rho, z in
+    // place of out
+    const double nout = list ? (double)nlist : (double)bout.Vh;
+    double entries = nout + (list ? (double)nread : hop_read_sites(bin, bout) / 2) +
                      (aux ? box_overlap(baux, bout) / 2 : 0);
-    if (cg) entries += (double)bout.Vh * (cg->cg_first ? 3 : 4);
+    if (cg) entries += nout * (cg->cg_first ? 3 : 4);
     const double bytes = (double)D.ndom * c->Ls * entries * S::bytes_spinor +
-                         (double)D.ndom * bout.Vh * 8 * S::bytes_link;
+                         (double)D.ndom * nout * 8 * S::bytes_link;
     Timed t(c, cg ? MSPCG_KC_HOPDOMCG : MSPCG_KC_HOPDOM, bytes, st);
     return launch_hop<S>(a, c->Ls, D.ndom, dag, st);
 }
@@ -322,7 +389,7 @@ static int dom_fived(mspcg_ctx* c, Field<S> out, CField<S> in, long Vh, const Fi
 
 // w = A_s p for every block: P_s Mhat_D^+ Mhat_D p (p supported on the block).
 // partials (optional) receive per-domain |Mhat_D p|^2 = <p, A_s p>, laid out
-// [ndom][hop_grid_x(pad2.Vh)].
+// [ndom][hop_grid_x(n_y)] (pad2.Vh in place of n_y when pad = 0).
 template <class S>
 int block_A(mspcg_ctx* c, Field<S> w, CField<S> p, double* partials, const int* done,
             hipStream_t st) {
@@ -346,13 +413,13 @@ int block_A(mspcg_ctx* c, Field<S> w, CField<S> p, double* partials, const int* 
     if ((e = dom_hop<S>(c, u, D.pad1, cfield(t), D.interior, 1, false, P.X, nullptr, D.interior,
                         P.id, nullptr, done, st)))
         return e;
-    // y = M5op p - D_h^eo u / 4  (even, pad 2) = Mhat_D p
+    // y = M5op p - D_h^eo u / 4  (even, pad 2, within distance 2) = Mhat_D p
     if ((e = dom_hop<S>(c, y, D.pad2, cfield(u), D.pad1, 0, false, m14, &p, D.interior, P.M5,
-                        partials, done, st)))
+                        partials, done, st, nullptr, D.list_y, D.n_y, D.rd_y)))
         return e;
-    // v = X^+ Dd^oe y  (odd, pad 1)
+    // v = X^+ Dd^oe y  (odd, pad 1, within distance 1)
     if ((e = dom_hop<S>(c, v, D.pad1, cfield(y), D.pad2, 1, true, P.Xdag, nullptr, D.interior,
-                        P.id, nullptr, done, st)))
+                        P.id, nullptr, done, st, nullptr, D.list_v, D.n_v, D.rd_v)))
         return e;
     // w = M5op^+ y - B^+ Dd^eo v / 4  (even, block)
     CField<S> yc = cfield(y);
@@ -395,13 +462,13 @@ static int block_cg_step(mspcg_ctx* c, Field<S> p, Field<S> rho, Field<S> z,
                         P.id, nullptr, done, st)))
         return e;
     if ((e = dom_hop<S>(c, y, D.pad2, cfield(u), D.pad1, 0, false, m14, &pc, D.interior, P.M5,
-                        part, done, st)))
+                        part, done, st, nullptr, D.list_y, D.n_y, D.rd_y)))
         return e;
     hipLaunchKernelGGL(inner_alpha, dim3(D.ndom), dim3(kThreads), 0, st, sc, part, (int)hop_np,
                        done);
     if (last_error()) return MSPCG_EHIP;
     if ((e = dom_hop<S>(c, v, D.pad1, cfield(y), D.pad2, 1, true, P.Xdag, nullptr, D.interior,
-                        P.id, nullptr, done, st)))
+                        P.id, nullptr, done, st, nullptr, D.list_v, D.n_v, D.rd_v)))
         return e;
     HopArgs<S> cg;
     memset(&cg, 0, sizeof(cg));
@@ -441,7 +508,7 @@ static int precond_core(mspcg_ctx* c, int l, CField<F64> r, Field<F64> z, const 
     Field<S> zz = half_field<S>(c, pf + "z", D.ndom * nd);
     if (!rho.data || !p.data || !zz.data) return MSPCG_ENOMEM;
     InnerScalars sc = inner_scalars(c);
-    const long hop_np = hop_grid_x<S>(D.pad2.Vh, Ls);
+    const long hop_np = hop_grid_x<S>(D.list_y ? D.n_y : D.pad2.Vh, Ls);
     const int spb = kThreads / Ls;
     const long start_np = (D.interior.Vh + spb - 1) / spb;
     const long vec_np = (nd + kThreads - 1) / kThreads;
@@ -488,7 +555,7 @@ size_t precond_partials_need(mspcg_ctx* c) {
     const Domains& D = c->dom;
     const int Ls = c->Ls;
     const long nd = D.interior.Vh * Ls;
-    const long hop_np = hop_grid_x<F64>(D.pad2.Vh, Ls);
+    const long hop_np = hop_grid_x<F64>(D.list_y ? D.n_y : D.pad2.Vh, Ls);
     const int spb = kThreads / Ls;
     const long start_np = (D.interior.Vh + spb - 1) / spb;
     const long vec_np = (nd + kThreads - 1) / kThreads;
