@@ -112,7 +112,9 @@ enum {
  * is evaluated: pad >= 2 gives exactly the paper's A_s = P_s A P_s (Fig. 3:
  * the diagonal block of A, including the paths that leave the block and come
  * back); pad = 0 drops every hop between blocks (A_s = Mhat_s^+ Mhat_s with
- * a Dirichlet-cut Mhat_s); pad = 1 lies in between. */
+ * a Dirichlet-cut Mhat_s); pad = 1 lies in between.  With FP16 local solves
+ * one padded block must hold fewer than 2^24 sites per parity and under 4 GB
+ * per FP16 field (MSPCG_EUNSUPPORTED otherwise). */
 typedef struct {
     int block[4];
     int pad;

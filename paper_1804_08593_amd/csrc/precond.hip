@@ -231,6 +231,7 @@ int domains_setup(mspcg_ctx* c, const mspcg_blocking& bk, int prec, hipStream_t 
     bool same = D.built && D.prec == prec && D.pad == bk.pad;
     for (int m = 0; m < 4; ++m) same = same && D.blk[m] == bk.block[m];
     if (same) return 0;
+    D.built = false;  // until every field below describes the new blocking
     if (prec != MSPCG_FP16 && prec != MSPCG_FP32 && prec != MSPCG_FP64) return MSPCG_EINVAL;
     if (bk.pad < 0 || bk.pad > 2) return MSPCG_EINVAL;
     int ndom = 1;
@@ -250,6 +251,10 @@ int domains_setup(mspcg_ctx* c, const mspcg_blocking& bk, int prec, hipStream_t 
     D.pad1 = dom_box(c, D, bk.pad < 1 ? bk.pad : 1);
     D.pad2 = dom_box(c, D, bk.pad < 2 ? bk.pad : 2);
     D.Vh_int = D.interior.Vh;
+    // FP16 hops address a domain's sites with 32-bit offsets
+    if (prec == MSPCG_FP16 &&
+        (D.pad2.Vh >= (1L << 24) || D.pad2.Vh * c->Ls * (long)Chunk<F16>::K * 16 > 0xffffffffL))
+        return MSPCG_EUNSUPPORTED;
     if (D.links) (void)hipFree(D.links);
     D.links = nullptr;
     size_t esz = prec == MSPCG_FP64 ? sizeof(double2) : (prec == MSPCG_FP32 ? sizeof(float2) : sizeof(__half2));
