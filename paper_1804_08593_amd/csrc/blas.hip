@@ -94,16 +94,13 @@ void fived_launch_ls(const FiveDArgs<S>& a, int ndom, hipStream_t st) {
 // One workgroup per output: fixed-order strided sums, then a fixed tree.
 __global__ void reduce_rows_kernel(const double* partials, int nparts, double* out) {
     const double* p = partials + (long)blockIdx.x * nparts;
-    double v = 0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) v += p[i];
+    const double v = strided_sum(p, nparts);
     block_reduce_store(v, out + blockIdx.x);
 }
 
 __device__ double block_sum_all(const double* p, int n) {
     __shared__ double red2[kThreads];
-    double v = 0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
-    red2[threadIdx.x] = v;
+    red2[threadIdx.x] = strided_sum(p, n);
     __syncthreads();
     for (int o = blockDim.x / 2; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) red2[threadIdx.x] += red2[threadIdx.x + o];

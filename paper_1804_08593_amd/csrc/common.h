@@ -121,6 +121,25 @@ __device__ __forceinline__ unsigned f2h(float re, float im) {
     return u;
 }
 
+// This thread's part of a fixed-order strided sum: p[t] + p[t + B] + ... for
+// t = threadIdx.x, B = blockDim.x, added in that order.  Loads are issued in
+// groups of eight before their adds so that they overlap instead of each
+// waiting out a full memory latency; the order of the adds is unchanged.
+__device__ __forceinline__ double strided_sum(const double* p, int n) {
+    const int B = (int)blockDim.x;
+    double v = 0;
+    int i = (int)threadIdx.x;
+    for (; i + 7 * B < n; i += 8 * B) {
+        double t[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) t[k] = p[i + k * B];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v += t[k];
+    }
+    for (; i < n; i += B) v += p[i];
+    return v;
+}
+
 // The undecoded 16-byte chunks of one entry (+ its FP16 scale): loading raw
 // chunks first and decoding later lets a thread keep several neighbour
 // spinors in flight in few registers.

@@ -58,9 +58,7 @@ struct InnerScalars {
 // one workgroup per domain: fixed-order sum of that domain's partials
 __device__ double domain_sum(const double* p, int n) {
     __shared__ double red2[kThreads];
-    double v = 0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
-    red2[threadIdx.x] = v;
+    red2[threadIdx.x] = strided_sum(p, n);
     __syncthreads();
     for (int o = blockDim.x / 2; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) red2[threadIdx.x] += red2[threadIdx.x + o];
