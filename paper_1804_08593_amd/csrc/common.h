@@ -298,20 +298,26 @@ struct Box {
 // The domain origin has even global parity (domains start at multiples of
 // even block extents), so the global parity of a local site is
 // (x + y + z + t + sum(off)) mod 2.
+// Box site counts stay below 2^31 (checked when contexts and domains are
+// made), so the index arithmetic is 32-bit.
 __device__ __forceinline__ void box_coords(const Box& b, long cb, int par, int c[4]) {
-    const int hx = b.E[0] >> 1;
-    long r = cb / hx;
-    const int xh = (int)(cb - r * hx);
-    c[1] = (int)(r % b.E[1]);
-    r /= b.E[1];
-    c[2] = (int)(r % b.E[2]);
-    c[3] = (int)(r / b.E[2]);
+    const unsigned hx = (unsigned)b.E[0] >> 1, e1 = (unsigned)b.E[1], e2 = (unsigned)b.E[2];
+    const unsigned u = (unsigned)cb;
+    const unsigned r = u / hx;
+    const int xh = (int)(u - r * hx);
+    const unsigned r2 = r / e1;
+    c[1] = (int)(r - r2 * e1);
+    const unsigned r3 = r2 / e2;
+    c[2] = (int)(r2 - r3 * e2);
+    c[3] = (int)r3;
     const int so = b.off[0] + b.off[1] + b.off[2] + b.off[3];
     c[0] = 2 * xh + ((par + c[1] + c[2] + c[3] + so) & 1);
 }
 
 __device__ __forceinline__ long box_cb(const Box& b, const int c[4]) {
-    return ((((long)c[3] * b.E[2] + c[2]) * b.E[1] + c[1]) * b.E[0] + c[0]) >> 1;
+    const unsigned lex =
+        (((unsigned)c[3] * b.E[2] + c[2]) * (unsigned)b.E[1] + c[1]) * (unsigned)b.E[0] + c[0];
+    return (long)(lex >> 1);
 }
 
 // Dense per-chirality 5D operators are applied as short programs of

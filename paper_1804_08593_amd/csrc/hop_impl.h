@@ -69,11 +69,10 @@ __device__ __forceinline__ void project(const cx<T> (&p)[12], cx<T> (&h)[6], T o
 }
 
 // acc_up += k w ; acc_dn += sig k e_mu^+ w with k the neighbour's FP16 scale
-// (1 for unscaled storage), each update one fused multiply-add; FIRST assigns
-// instead of adding.
-template <int MU, int SIG, bool FIRST, typename T>
+// (1 for unscaled storage), each update one fused multiply-add.
+template <int MU, int SIG, typename T>
 __device__ __forceinline__ void reconstruct(const cx<T> (&w)[6], cx<T> (&acc)[12], T k) {
-    auto add = [&](T& a, T x) { a = FIRST ? k * x : fmadd(k, x, a); };
+    auto add = [&](T& a, T x) { a = fmadd(k, x, a); };
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const cx<T> w0 = w[c], w1 = w[3 + c];
@@ -115,9 +114,9 @@ __device__ __forceinline__ cx<typename S::real> elem_cx(typename S::elem e) {
     }
 }
 
-// acc (+)= k (1 + SIG g_mu) U p   (u: the 3x3 link, row-major; k as in
+// acc += k (1 + SIG g_mu) U p   (u: the 3x3 link, row-major; k as in
 // reconstruct)
-template <class S, int MU, int SIG, bool FIRST>
+template <class S, int MU, int SIG>
 __device__ __forceinline__ void dir_apply(const cx<typename S::real> (&p)[12],
                                           const cx<typename S::real> (&u)[9],
                                           cx<typename S::real> (&acc)[12],
@@ -135,7 +134,7 @@ __device__ __forceinline__ void dir_apply(const cx<typename S::real> (&p)[12],
             cfma(t, u[i * 3 + 2], h[sp * 3 + 2]);
             w[sp * 3 + i] = t;
         }
-    reconstruct<MU, SIG, FIRST>(w, acc, k);
+    reconstruct<MU, SIG>(w, acc, k);
 }
 
 // A global-memory pointer with the same value in every lane of the wave,
@@ -304,16 +303,17 @@ __global__ __launch_bounds__(256, (hop_min_waves<S, LS, EPA, CG>())) void hop_ke
                 tb.E[m] = a.tile[m];
                 tb.off[m] = 0;
             }
-            const long th = (long)a.tile[0] * a.tile[1] * a.tile[2] * a.tile[3] / 2;
-            long st = t_lin / th;
-            const long w = t_lin - st * th;
+            const unsigned th = (unsigned)(a.tile[0] * a.tile[1] * a.tile[2] * a.tile[3] / 2);
+            unsigned st = (unsigned)t_lin / th;
+            const unsigned w = (unsigned)t_lin - st * th;
             const int so = g.out.off[0] + g.out.off[1] + g.out.off[2] + g.out.off[3];
             box_coords(tb, w, (g.out_par + so) & 1, oc);
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                const int nt = g.out.E[m] / a.tile[m];
-                oc[m] += (int)(st % nt) * a.tile[m];
-                st /= nt;
+                const unsigned nt = (unsigned)(g.out.E[m] / a.tile[m]);
+                const unsigned q = st / nt;
+                oc[m] += (int)(st - q * nt) * a.tile[m];
+                st = q;
             }
             cb = box_cb(g.out, oc);
         } else {
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(256, (hop_min_waves<S, LS, EPA, CG>())) void hop_ke
                         for (int k = 0; k < 9; ++k) u[k] = load_link<S, MSPCG_HOP_NT>(gl + LD + k);
                     }
                     const T k = S::has_scale ? (T)raw[j].sc : (T)1;
-                    dir_apply<S, MU, FWD ? SF : SB, false>(p, u, acc, k, one);
+                    dir_apply<S, MU, FWD ? SF : SB>(p, u, acc, k, one);
                 }
             });
         });
@@ -623,13 +623,11 @@ static void launch_ls(const HopArgs<S>& a, int ndom, bool dag, hipStream_t st) {
 }
 
 template <class S>
-int launch_hop(const HopArgs<S>& a0, int Ls, int ndom, bool dag, hipStream_t st) {
-    if (a0.cg_r.data && (!dag || !a0.partials)) return -1;
-    HopArgs<S> a = a0;
+int launch_hop(const HopArgs<S>& a, int Ls, int ndom, bool dag, hipStream_t st) {
+    if (a.cg_r.data && (!dag || !a.partials)) return -1;
+    // FP16-storage hops address a domain's input sites with 32-bit offsets
     const long site_bytes = (long)Ls * Chunk<S>::K * 16;
-    a.off32 = a.g.in.Vh < (1L << 24) && a.g.in.Vh * site_bytes <= 0xffffffffL;
-    // FP16-storage hops address neighbours with 32-bit offsets only
-    if (S::has_scale && !a.off32) return -1;
+    if (S::has_scale && (a.g.in.Vh >= (1L << 24) || a.g.in.Vh * site_bytes > 0xffffffffL)) return -1;
     switch (Ls) {
 #define MSPCG_CASE(L) \
     case L: launch_ls<S, L>(a, ndom, dag, st); break;

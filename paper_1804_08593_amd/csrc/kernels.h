@@ -52,10 +52,6 @@ struct HopArgs {
     // is ignored then
     const int* site_list;
     long n_list;
-    // set by launch_hop: one domain's input box spans < 4 GB and < 2^24 sites
-    // (required for FP16 storage, whose neighbour addresses are 32-bit offsets
-    // from the domain's base)
-    int off32;
 };
 
 template <class S>

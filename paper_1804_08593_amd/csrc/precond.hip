@@ -249,6 +249,7 @@ int domains_setup(mspcg_ctx* c, const mspcg_blocking& bk, int prec, hipStream_t 
     D.pad1 = dom_box(c, D, bk.pad < 1 ? bk.pad : 1);
     D.pad2 = dom_box(c, D, bk.pad < 2 ? bk.pad : 2);
     D.Vh_int = D.interior.Vh;
+    if (D.pad2.Vh >= (1L << 31)) return MSPCG_EUNSUPPORTED;  // 32-bit site indices
     // FP16 hops address a domain's sites with 32-bit offsets
     if (prec == MSPCG_FP16 &&
         (D.pad2.Vh >= (1L << 24) || D.pad2.Vh * c->Ls * (long)Chunk<F16>::K * 16 > 0xffffffffL))
