@@ -167,9 +167,16 @@ size_t precond_partials_need(mspcg_ctx* c);
 template <class S>
 int precond_apply(mspcg_ctx* c, int inner_iters, CField<F64> r_e, Field<F64> z_e,
                   hipStream_t st, int* inner_done);
+// Optional output of precond_apply_flag: with l > 0 the workgroup partials of
+// Re<z, r> and Re<z, q> are left in ctx->partials ([0, np) and [np, 2 np));
+// np stays 0 when they were not formed (l = 0).
+struct PrecondDots {
+    CField<F64> r, q;
+    long np;
+};
 template <class S>
 int precond_apply_flag(mspcg_ctx* c, int l, CField<F64> r, Field<F64> z, const int* done,
-                       hipStream_t st);
+                       hipStream_t st, PrecondDots* dots = nullptr);
 template <class S>
 int kblock_apply(mspcg_ctx* c, CField<F64> p_e, Field<F64> q_e, hipStream_t st);
 // w = A_s p on every block (domain layout, precision S)

@@ -100,6 +100,13 @@ int launch_global_to_domain(CField<SG> g, Field<SD> dom, const int dims[4], cons
 template <class SD, class SG>
 int launch_domain_to_global(CField<SD> dom, Field<SG> g, const int dims[4], const int blk[4],
                             const int nb[4], int Ls, int par, hipStream_t st);
+// Even-parity domain_to_global into FP64 with the workgroup partials of
+// Re<z, r> (partials[0, np)) and Re<z, q> (partials[np, 2 np)); returns np,
+// or -1 on a launch error.
+template <class SD>
+long launch_domain_to_global_dots(CField<SD> dom, Field<F64> z, CField<F64> r, CField<F64> q,
+                                  const int dims[4], const int blk[4], const int nb[4], int Ls,
+                                  double* partials, hipStream_t st);
 
 // Links for the link box of every domain (whole lattice: one domain, pad 0).
 // U: boundary complex128 [4][Lt][Lz][Ly][Lx][3][3].

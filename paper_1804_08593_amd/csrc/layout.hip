@@ -136,6 +136,53 @@ __global__ void domain_to_global_kernel(CField<SD> dom, Field<SG> gl, DomGrid g,
     store_spinor<SG>(gl, gcb * Ls + s, w);
 }
 
+// domain_to_global into an FP64 field z plus the workgroup partials of
+// Re<z, r> and Re<z, q> (r, q: FP64 fields of the same layout as z), laid
+// out [domain][workgroup] for each of the two sums, np entries apart.
+template <class SD>
+__global__ void domain_to_global_dots_kernel(CField<SD> dom, Field<F64> gl, CField<F64> r,
+                                             CField<F64> q, DomGrid g, int Ls, long Vhb,
+                                             double* partials, long np) {
+    __shared__ double ra[kThreads], rb[kThreads];
+    const long cb = (long)blockIdx.x * (blockDim.x / Ls) + threadIdx.x / Ls;
+    const int s = threadIdx.x % Ls;
+    const int d = blockIdx.y;
+    double a = 0, b = 0;
+    if (threadIdx.x < (blockDim.x / Ls) * Ls && cb < Vhb) {
+        const long gcb = dom_to_global_cb(g, d, cb, 0);
+        cx<typename SD::real> v[12];
+        load_spinor<SD>(dom, ((long)d * Vhb + cb) * Ls + s, v);
+        cx<double> w[12], rv[12], qv[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) w[c] = {(double)v[c].re, (double)v[c].im};
+        store_spinor<F64>(gl, gcb * Ls + s, w);
+        load_spinor<F64>(r, gcb * Ls + s, rv);
+        load_spinor<F64>(q, gcb * Ls + s, qv);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            a += w[c].re * rv[c].re + w[c].im * rv[c].im;
+            b += w[c].re * qv[c].re + w[c].im * qv[c].im;
+        }
+    }
+    // fixed-order tree over the workgroup (blockDim.x need not be a power of 2)
+    const int t = threadIdx.x;
+    ra[t] = a;
+    rb[t] = b;
+    __syncthreads();
+    for (int o = kThreads / 2; o > 0; o >>= 1) {
+        if (t < o && t + o < (int)blockDim.x) {
+            ra[t] += ra[t + o];
+            rb[t] += rb[t + o];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const long k = (long)d * gridDim.x + blockIdx.x;
+        partials[k] = ra[0];
+        partials[np + k] = rb[0];
+    }
+}
+
 // One thread per (domain, parity, link-box site, direction).
 template <class S>
 __global__ void pack_links_kernel(const double2* U, typename S::elem* out, DomGrid g, Box lb,
@@ -272,6 +319,21 @@ int launch_domain_to_global(CField<SD> dom, Field<SG> gl, const int dims[4], con
     return last_error();
 }
 
+template <class SD>
+long launch_domain_to_global_dots(CField<SD> dom, Field<F64> gl, CField<F64> r, CField<F64> q,
+                                  const int dims[4], const int blk[4], const int nb[4], int Ls,
+                                  double* partials, hipStream_t st) {
+    const DomGrid g = make_grid(dims, blk, nb);
+    const long Vhb = (long)blk[0] * blk[1] * blk[2] * blk[3] / 2;
+    const int spb = kThreads / Ls;
+    const int ndom = nb[0] * nb[1] * nb[2] * nb[3];
+    const long gx = nblocks(Vhb, spb);
+    const long np = gx * ndom;
+    hipLaunchKernelGGL((domain_to_global_dots_kernel<SD>), dim3((unsigned)gx, ndom),
+                       dim3(spb * Ls), 0, st, dom, gl, r, q, g, Ls, Vhb, partials, np);
+    return last_error() ? -1 : np;
+}
+
 template <class S>
 int launch_pack_links(const double2* U, typename S::elem* out, const int dims[4], const int blk[4],
                       const int nb[4], const Box& lb, int antiperiodic_t, hipStream_t st) {
@@ -300,6 +362,13 @@ int launch_convert(CField<SI> in, Field<SO> out, long n, hipStream_t st) {
 MSPCG_INST1(F64)
 MSPCG_INST1(F32)
 MSPCG_INST1(F16)
+#define MSPCG_INST_DOTS(S)                                                                         \
+    template long launch_domain_to_global_dots<S>(CField<S>, Field<F64>, CField<F64>, CField<F64>, \
+                                                  const int*, const int*, const int*, int,         \
+                                                  double*, hipStream_t);
+MSPCG_INST_DOTS(F64)
+MSPCG_INST_DOTS(F32)
+MSPCG_INST_DOTS(F16)
 #define MSPCG_INST2(A, B)                                                                          \
     template int launch_global_to_domain<A, B>(CField<A>, Field<B>, const int*, const int*,       \
                                                const int*, int, int, hipStream_t);                 \

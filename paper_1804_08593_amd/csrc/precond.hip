@@ -502,7 +502,7 @@ static InnerScalars inner_scalars(mspcg_ctx* c) {
 // may be null) skips the work once the outer solve has converged.
 template <class S>
 static int precond_core(mspcg_ctx* c, int l, CField<F64> r, Field<F64> z, const int* done,
-                        hipStream_t st) {
+                        hipStream_t st, PrecondDots* dots = nullptr) {
     const Domains& D = c->dom;
     const int Ls = c->Ls;
     const long nd = D.interior.Vh * Ls;  // (site, s) per domain
@@ -546,9 +546,17 @@ static int precond_core(mspcg_ctx* c, int l, CField<F64> r, Field<F64> z, const 
             if (last_error()) return MSPCG_EHIP;
         }
     }
-    Timed t(c, MSPCG_KC_BLAS, (double)D.ndom * nd * (192.0 + S::bytes_spinor), st);
+    // z written in FP64 from the domain copy (+ r and q read for the dots)
+    Timed t(c, MSPCG_KC_BLAS,
+            (double)D.ndom * nd * (192.0 + S::bytes_spinor + (dots && l > 0 ? 2 * 192.0 : 0.0)), st);
     if (l == 0) {
         return launch_zero(z.data, c->Nh, st) ? MSPCG_EHIP : 0;
+    }
+    if (dots) {
+        // z and the workgroup partials of Re<z, r>, Re<z, q> in one pass
+        dots->np = launch_domain_to_global_dots<S>(cfield(zz), z, dots->r, dots->q, c->L, D.blk,
+                                                   D.nb, Ls, c->partials, st);
+        return dots->np < 0 ? MSPCG_EHIP : 0;
     }
     if (launch_domain_to_global<S, F64>(cfield(zz), z, c->L, D.blk, D.nb, Ls, 0, st))
         return MSPCG_EHIP;
@@ -575,8 +583,8 @@ int precond_apply(mspcg_ctx* c, int l, CField<F64> r, Field<F64> z, hipStream_t 
 
 template <class S>
 int precond_apply_flag(mspcg_ctx* c, int l, CField<F64> r, Field<F64> z, const int* done,
-                       hipStream_t st) {
-    return precond_core<S>(c, l, r, z, done, st);
+                       hipStream_t st, PrecondDots* dots) {
+    return precond_core<S>(c, l, r, z, done, st, dots);
 }
 
 template <class S>
@@ -604,7 +612,7 @@ template int block_A<F16>(mspcg_ctx*, Field<F16>, CField<F16>, double*, const in
     template int precond_apply<S>(mspcg_ctx*, int, CField<F64>, Field<F64>, hipStream_t,   \
                                   int*);                                                    \
     template int precond_apply_flag<S>(mspcg_ctx*, int, CField<F64>, Field<F64>,           \
-                                       const int*, hipStream_t);                            \
+                                       const int*, hipStream_t, PrecondDots*);              \
     template int kblock_apply<S>(mspcg_ctx*, CField<F64>, Field<F64>, hipStream_t);
 MSPCG_PC(F64)
 MSPCG_PC(F32)

@@ -258,9 +258,14 @@ struct MSPCGSolver : Solver {
         int e;
         if ((e = cg_step<F64>(c, x, r, pp, q, cfield(z), true, true, &c->sc->done, st))) return e;
         if (launch_cg_beta(c->sc, c->partials, (int)nph, c->hist, cap, st)) return MSPCG_EHIP;
-        if ((e = precond_apply_flag<S>(c, l, cfield(r), z, &c->sc->done, st))) return e;
-        if (launch_dot2(z.data, r.data, q.data, c->Nh, c->partials, npb, st)) return MSPCG_EHIP;
-        if (launch_fpcg_beta(c->sc, c->partials, (int)npb, st)) return MSPCG_EHIP;
+        PrecondDots dots{cfield(r), cfield(q), 0};
+        if ((e = precond_apply_flag<S>(c, l, cfield(r), z, &c->sc->done, st, &dots))) return e;
+        long np = dots.np;
+        if (np == 0) {
+            if (launch_dot2(z.data, r.data, q.data, c->Nh, c->partials, npb, st)) return MSPCG_EHIP;
+            np = npb;
+        }
+        if (launch_fpcg_beta(c->sc, c->partials, (int)np, st)) return MSPCG_EHIP;
         return 0;
     }
     int after_poll(hipStream_t st) override {
