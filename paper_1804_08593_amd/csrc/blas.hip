@@ -45,6 +45,23 @@ __global__ __launch_bounds__(256) void fived_kernel(FiveDArgs<S> a) {
     if (active) {
         load_spinor_at<S>(a.in, ib, s, LS, v);
         if (a.xp_src.data) {
+            if (a.zd_z.data) {
+                // deferred solution update z (+)= alpha p with the old p
+                const T al = (T)a.zd_alpha[d];
+                cx<T> zv[12];
+                if (a.zd_first) {
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) zv[c] = {al * v[c].re, al * v[c].im};
+                } else {
+                    load_spinor_at<S>(cfield(a.zd_z), ib, s, LS, zv);
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) {
+                        zv[c].re += al * v[c].re;
+                        zv[c].im += al * v[c].im;
+                    }
+                }
+                store_spinor_at<S>(a.zd_z, ib, s, LS, zv);
+            }
             // search-direction update p = src + beta p, written back in place
             const T b = (T)(a.xp_beta ? a.xp_beta[d] : a.xp_sc->beta);
             cx<T> r[12];
@@ -73,11 +90,12 @@ __global__ __launch_bounds__(256) void fived_kernel(FiveDArgs<S> a) {
     double n2 = 0;
     if (active) {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            v[c] = lds[sl * SITE_STRIDE + s * 12 + c];
-            n2 += (double)v[c].re * v[c].re + (double)v[c].im * v[c].im;
-        }
+        for (int c = 0; c < 12; ++c) v[c] = lds[sl * SITE_STRIDE + s * 12 + c];
         store_spinor_at<S>(a.out, ib, s, LS, v);
+        if (a.partials) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) n2 += (double)v[c].re * v[c].re + (double)v[c].im * v[c].im;
+        }
     }
     if (a.partials) block_reduce_store(n2, a.partials + (long)d * gridDim.x + blockIdx.x);
 }

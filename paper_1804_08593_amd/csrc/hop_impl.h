@@ -549,20 +549,22 @@ __global__ __launch_bounds__(256, (hop_min_waves<S, LS, EPA, CG>())) void hop_ke
             }
             n2 = (double)t2;
             store_spinor_at<S>(a.cg_r, obase, s, LS, v);
-            cx<T> pv[12];
-            load_spinor_at<S>(a.cg_p, obase, s, LS, pv);
-            if (a.cg_first) {
+            if (a.cg_x.data) {
+                cx<T> pv[12];
+                load_spinor_at<S>(a.cg_p, obase, s, LS, pv);
+                if (a.cg_first) {
 #pragma unroll
-                for (int c = 0; c < 12; ++c) v[c] = {al * pv[c].re, al * pv[c].im};
-            } else {
-                load_spinor_at<S>(cfield(a.cg_x), obase, s, LS, v);
+                    for (int c = 0; c < 12; ++c) v[c] = {al * pv[c].re, al * pv[c].im};
+                } else {
+                    load_spinor_at<S>(cfield(a.cg_x), obase, s, LS, v);
 #pragma unroll
-                for (int c = 0; c < 12; ++c) {
-                    v[c].re += al * pv[c].re;
-                    v[c].im += al * pv[c].im;
+                    for (int c = 0; c < 12; ++c) {
+                        v[c].re += al * pv[c].re;
+                        v[c].im += al * pv[c].im;
+                    }
                 }
+                store_spinor_at<S>(a.cg_x, obase, s, LS, v);
             }
-            store_spinor_at<S>(a.cg_x, obase, s, LS, v);
         }
         block_sum_store<S, LS>(n2, a.partials + (long)d * gridDim.x + bx);
         return;

@@ -37,8 +37,9 @@ struct HopArgs {
     int tile[4];       // nonzero: traverse output sites in 4D tiles of this extent
     // optional CG update fused after the output is formed (the last hop of A,
     // whole lattice or block domains):
-    //   r -= alpha out ; x += alpha p (x = alpha p when cg_first) ;
-    //   partials = |r|^2 ; out is stored only when cg_keep_out.
+    //   r -= alpha out ; x += alpha p (x = alpha p when cg_first; no x update
+    //   when cg_x.data is null) ; partials = |r|^2 ; out is stored only when
+    //   cg_keep_out.
     //   alpha is cg_alpha[domain] when given, else cg_sc->alpha.
     Field<S> cg_r;
     Field<S> cg_x;
@@ -76,6 +77,11 @@ struct FiveDArgs {
     Field<S> xp_in;
     const DevScalars* xp_sc;
     const double* xp_beta;
+    // optional, with the update above: zd_z (+)= zd_alpha[domain] * (in before
+    // the update); zd_z = that product when zd_first
+    Field<S> zd_z;
+    const double* zd_alpha;
+    int zd_first;
 };
 template <class S>
 int launch_fived(const FiveDArgs<S>& a, int Ls, int ndom, hipStream_t st);

@@ -361,7 +361,7 @@ static int dom_hop(mspcg_ctx* c, Field<S> out, const Box& bout, CField<S> in, co
     const double nout = list ? (double)nlist : (double)bout.Vh;
     double entries = nout + (list ? (double)nread : hop_read_sites(bin, bout) / 2) +
                      (aux ? box_overlap(baux, bout) / 2 : 0);
-    if (cg) entries += nout * (cg->cg_first ? 3 : 4);
+    if (cg) entries += nout * (cg->cg_x.data ? (cg->cg_first ? 3 : 4) : 1);
     const double bytes = (double)D.ndom * c->Ls * entries * S::bytes_spinor +
                          (double)D.ndom * nout * 8 * S::bytes_link;
     Timed t(c, cg ? MSPCG_KC_HOPDOMCG : MSPCG_KC_HOPDOM, bytes, st);
@@ -371,7 +371,9 @@ static int dom_hop(mspcg_ctx* c, Field<S> out, const Box& bout, CField<S> in, co
 template <class S>
 static int dom_fived(mspcg_ctx* c, Field<S> out, CField<S> in, long Vh, const FiveDProg& p,
                      const int* done, hipStream_t st, const Field<S>* xp_in = nullptr,
-                     CField<S> xp_src = {}, const double* xp_beta = nullptr) {
+                     CField<S> xp_src = {}, const double* xp_beta = nullptr,
+                     const Field<S>* zd_z = nullptr, const double* zd_alpha = nullptr,
+                     int zd_first = 0) {
     FiveDArgs<S> a;
     memset(&a, 0, sizeof(a));
     a.in = in;
@@ -385,9 +387,14 @@ static int dom_fived(mspcg_ctx* c, Field<S> out, CField<S> in, long Vh, const Fi
         a.xp_in = *xp_in;
         a.xp_src = xp_src;
         a.xp_beta = xp_beta;
+        if (zd_z) {  // z (+)= alpha[domain] in, with in before that update
+            a.zd_z = *zd_z;
+            a.zd_alpha = zd_alpha;
+            a.zd_first = zd_first;
+        }
     }
-    Timed t(c, MSPCG_KC_FIVED, (double)c->dom.ndom * Vh * c->Ls * S::bytes_spinor * (xp_in ? 4 : 2),
-            st);
+    const int entries = (xp_in ? 4 : 2) + (xp_in && zd_z ? (zd_first ? 1 : 2) : 0);
+    Timed t(c, MSPCG_KC_FIVED, (double)c->dom.ndom * Vh * c->Ls * S::bytes_spinor * entries, st);
     return launch_fived<S>(a, c->Ls, c->dom.ndom, st);
 }
 
@@ -434,12 +441,15 @@ int block_A(mspcg_ctx* c, Field<S> w, CField<S> p, double* partials, const int* 
 // One local CG step on every block with the vector updates fused into the
 // block operator: p = rho + beta p rides on t = B p (it > 0), alpha =
 // gam / |Mhat_D p|^2 per block is formed after the Mhat half, and the last
-// hop does rho -= alpha w, z += alpha p (z = alpha p when it == 0) with the
-// per-block |rho|^2 partials ([ndom][hop_grid_x(interior.Vh)]); w is never
-// stored.  pq_partials receive |Mhat_D p|^2 laid out [ndom][hop_np].
+// hop does rho -= alpha w with the per-block |rho|^2 partials
+// ([ndom][hop_grid_x(interior.Vh)]); w is never stored.  The solution update
+// z += alpha p of step it is deferred to the B kernel of step it + 1, which
+// reads the old p anyway (z = alpha p there when it + 1 == 1); the last step
+// (it == l - 1) does it in its last hop.  pq_partials receive |Mhat_D p|^2
+// laid out [ndom][hop_np].
 template <class S>
 static int block_cg_step(mspcg_ctx* c, Field<S> p, Field<S> rho, Field<S> z,
-                         const InnerScalars& sc, int it, double* part, long hop_np,
+                         const InnerScalars& sc, int it, int l, double* part, long hop_np,
                          const int* done, hipStream_t st) {
     const Domains& D = c->dom;
     const int Ls = c->Ls;
@@ -457,7 +467,9 @@ static int block_cg_step(mspcg_ctx* c, Field<S> p, Field<S> rho, Field<S> z,
     const CField<S> pc = cfield(p);
     int e;
     if (it > 0) {
-        if ((e = dom_fived<S>(c, t, pc, D.interior.Vh, P.B, done, st, &p, cfield(rho), sc.beta)))
+        // sc.a still holds the step length of step it - 1 here
+        if ((e = dom_fived<S>(c, t, pc, D.interior.Vh, P.B, done, st, &p, cfield(rho), sc.beta, &z,
+                              sc.a, it == 1 ? 1 : 0)))
             return e;
     } else if ((e = dom_fived<S>(c, t, pc, D.interior.Vh, P.B, done, st))) {
         return e;
@@ -477,7 +489,7 @@ static int block_cg_step(mspcg_ctx* c, Field<S> p, Field<S> rho, Field<S> z,
     HopArgs<S> cg;
     memset(&cg, 0, sizeof(cg));
     cg.cg_r = rho;
-    cg.cg_x = z;
+    if (it == l - 1) cg.cg_x = z;  // earlier steps: deferred to the next B kernel
     cg.cg_p = pc;
     cg.cg_alpha = sc.a;
     cg.cg_first = it == 0 ? 1 : 0;
@@ -539,7 +551,7 @@ static int precond_core(mspcg_ctx* c, int l, CField<F64> r, Field<F64> z, const 
     // partials of the fused update: one per workgroup of the interior hop
     const long upd_np = hop_grid_x<S>(D.interior.Vh, Ls);
     for (int it = 0; it < l; ++it) {
-        if ((e = block_cg_step<S>(c, p, rho, zz, sc, it, part, hop_np, done, st))) return e;
+        if ((e = block_cg_step<S>(c, p, rho, zz, sc, it, l, part, hop_np, done, st))) return e;
         if (it + 1 < l) {
             hipLaunchKernelGGL(inner_beta, dim3(D.ndom), dim3(kThreads), 0, st, sc, part,
                                (int)upd_np, done);
