@@ -151,12 +151,23 @@ struct RawSpinor {
 
 // Entry (base + s) with base = site*ls.  Callers with a compile-time Ls pass
 // it as `ls` so the index arithmetic folds.
-template <class S>
+// NT: the entry is read once (streamed), so its lines are not kept in cache.
+template <class S, bool NT = false>
 __device__ __forceinline__ void load_raw_at(CField<S> f, long base, int s, int ls, RawSpinor<S>& r) {
     const nt_u4* p = reinterpret_cast<const nt_u4*>(f.data) + base * Chunk<S>::K + s;
 #pragma unroll
-    for (int k = 0; k < Chunk<S>::K; ++k) r.c[k] = p[(long)k * ls];
-    if constexpr (S::has_scale) r.sc = f.scale[base + s];
+    for (int k = 0; k < Chunk<S>::K; ++k) {
+        if constexpr (NT)
+            r.c[k] = __builtin_nontemporal_load(p + (long)k * ls);
+        else
+            r.c[k] = p[(long)k * ls];
+    }
+    if constexpr (S::has_scale) {
+        if constexpr (NT)
+            r.sc = __builtin_nontemporal_load(f.scale + base + s);
+        else
+            r.sc = f.scale[base + s];
+    }
 }
 
 template <class S>
@@ -187,11 +198,11 @@ __device__ __forceinline__ void decode_raw(const RawSpinor<S>& r, cx<typename S:
     }
 }
 
-template <class S>
+template <class S, bool NT = false>
 __device__ __forceinline__ void load_spinor_at(CField<S> f, long base, int s, int ls,
                                                cx<typename S::real> (&v)[12]) {
     RawSpinor<S> r;
-    load_raw_at<S>(f, base, s, ls, r);
+    load_raw_at<S, NT>(f, base, s, ls, r);
     decode_raw<S>(r, v);
 }
 

@@ -497,7 +497,7 @@ __global__ __launch_bounds__(256, (hop_min_waves<S, LS, EPA, CG>())) void hop_ke
                 ac[m] = gc[m] - g.aux.off[m];
                 in = in && ac[m] >= 0 && ac[m] < g.aux.E[m];
             }
-            if (in) load_spinor_at<S>(a.aux, ((long)d * g.aux.Vh + box_cb(g.aux, ac)) * LS, s, LS, x);
+            if (in) load_spinor_at<S, MSPCG_HOP_NT>(a.aux, ((long)d * g.aux.Vh + box_cb(g.aux, ac)) * LS, s, LS, x);
         }
         if (a.pa.identity) {
 #pragma unroll
@@ -538,7 +538,7 @@ __global__ __launch_bounds__(256, (hop_min_waves<S, LS, EPA, CG>())) void hop_ke
             if (a.cg_keep_out) store_spinor_at<S, MSPCG_HOP_NT>(a.out, obase, s, LS, res);
             const T al = (T)(a.cg_alpha ? a.cg_alpha[d] : a.cg_sc->alpha);
             cx<T> v[12];
-            load_spinor_at<S>(cfield(a.cg_r), obase, s, LS, v);
+            load_spinor_at<S, MSPCG_HOP_NT>(cfield(a.cg_r), obase, s, LS, v);
             T t2 = 0;  // one entry's 24 squares in the arithmetic type
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
@@ -551,12 +551,12 @@ __global__ __launch_bounds__(256, (hop_min_waves<S, LS, EPA, CG>())) void hop_ke
             store_spinor_at<S>(a.cg_r, obase, s, LS, v);
             if (a.cg_x.data) {
                 cx<T> pv[12];
-                load_spinor_at<S>(a.cg_p, obase, s, LS, pv);
+                load_spinor_at<S, MSPCG_HOP_NT>(a.cg_p, obase, s, LS, pv);
                 if (a.cg_first) {
 #pragma unroll
                     for (int c = 0; c < 12; ++c) v[c] = {al * pv[c].re, al * pv[c].im};
                 } else {
-                    load_spinor_at<S>(cfield(a.cg_x), obase, s, LS, v);
+                    load_spinor_at<S, MSPCG_HOP_NT>(cfield(a.cg_x), obase, s, LS, v);
 #pragma unroll
                     for (int c = 0; c < 12; ++c) {
                         v[c].re += al * pv[c].re;
