@@ -22,8 +22,9 @@ struct Cand {
 
 std::vector<Cand> candidates(const int L[4]) {
     std::vector<Cand> v;
-    const int opts[][4] = {{0, 0, 0, 0}, {8, 4, 4, 4}, {L[0], 4, 4, 4}, {8, 8, 4, 4},
-                           {4, 4, 4, 4}, {L[0], L[1], 2, 2}, {8, 8, 8, 8}};
+    const int opts[][4] = {{0, 0, 0, 0}, {8, 4, 4, 4},   {L[0], 4, 4, 4}, {8, 8, 4, 4},
+                           {4, 4, 4, 4}, {L[0], L[1], 2, 2}, {8, 8, 8, 8},   {8, 8, 8, 4},
+                           {8, 8, 4, 8}, {4, 8, 8, 8},   {12, 12, 12, 12}, {8, 8, 8, 16}};
     for (auto& o : opts) {
         Cand c;
         c.remap = 1;
