@@ -76,6 +76,7 @@ def _load():
         lib.orc_prepare.argtypes = [P, P, P, P, P]
         lib.orc_reconstruct.argtypes = [P, P, P, P]
         lib.orc_force.argtypes = [P, P, P, P, P]
+        lib.orc_dwf_sites.argtypes = [P, P, P, P, P, L]
         _lib = lib
     return _lib
 
@@ -188,6 +189,17 @@ def dwf(act: Action, U, psi, dagger=False, block=None) -> np.ndarray:
     out = np.empty_like(psi)
     c = act.cstruct()
     _load().orc_dwf(ctypes.byref(c), _ivec(block), _p(U), _p(psi), _p(out), int(dagger))
+    return out
+
+
+def dwf_sites(act: Action, U, psi, sites) -> np.ndarray:
+    """D psi at the given lexicographic output sites only: [Ls][nsites][4][3]."""
+    U = _f(U, act.gshape)
+    psi = _f(psi, act.fshape)
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    out = np.empty((act.Ls, len(sites), 4, 3), dtype=np.complex128)
+    c = act.cstruct()
+    _load().orc_dwf_sites(ctypes.byref(c), _p(U), _p(psi), _p(out), _p(sites), len(sites))
     return out
 
 
@@ -341,7 +353,45 @@ def _block_dot(u, v, ids, nblk) -> np.ndarray:
             + 1j * np.bincount(ids.ravel(), weights=site.imag.ravel(), minlength=nblk))
 
 
-def block_precond_op(act: Action, U, p, block, mode: str = "literal") -> np.ndarray:
+def domain_mask(act: Action, block, k: int, pad: int) -> np.ndarray:
+    """Sites of block k widened by `pad` sites on both sides of every direction
+    in which the lattice holds more than one block (a direction that the block
+    spans is kept whole), as a boolean [Lt][Lz][Ly][Lx] mask.  Distances are
+    periodic; the widened block must not reach around onto itself."""
+    Lx, Ly, Lz, Lt = act.dims
+    nb = [act.dims[m] // block[m] for m in range(4)]
+    kk = [0] * 4
+    r = k
+    for m in range(4):
+        kk[m] = r % nb[m]
+        r //= nb[m]
+    coords = np.meshgrid(np.arange(Lt), np.arange(Lz), np.arange(Ly), np.arange(Lx),
+                         indexing="ij")[::-1]  # x, y, z, t
+    inside = np.ones((Lt, Lz, Ly, Lx), dtype=bool)
+    for m in range(4):
+        if nb[m] == 1:
+            continue
+        if act.dims[m] - block[m] < 2 * pad:
+            raise ValueError("padded block wraps onto itself")
+        rel = (coords[m] - kk[m] * block[m] + pad) % act.dims[m]
+        inside &= rel < block[m] + 2 * pad
+    return inside
+
+
+def domain_schur(act: Action, U, y, omega, dagger=False) -> np.ndarray:
+    """Mhat_Omega (or its adjoint): the even-odd Schur complement of the
+    principal submatrix of D on the site set Omega, from the same definition
+    as schur() with D replaced by P_Omega D P_Omega (every hop into or out of
+    Omega dropped).  omega: boolean [Lt][Lz][Ly][Lx]."""
+    m = omega[None, ..., None, None]
+    Dw = lambda v: m * dwf(act, U, m * v, dagger)
+    y = parity_mask(act, y, 0)
+    t = Dw(y)
+    w = m5(act, parity_mask(act, t, 1), "M5invdag" if dagger else "M5inv")
+    return parity_mask(act, t - Dw(w), 0)
+
+
+def block_precond_op(act: Action, U, p, block, mode: str = "literal", pad: int = 2) -> np.ndarray:
     """The preconditioner K = (+)_s A_s applied to p (Sec. 2.3 eq. (5), Fig. 3).
 
     mode "literal": A_s = P_s A P_s, the diagonal block of A = Mhat^+ Mhat with
@@ -349,20 +399,32 @@ def block_precond_op(act: Action, U, p, block, mode: str = "literal") -> np.ndar
       keeps the paths that leave block s and come back.  Computed from the
       definition: one application of A per block, masked before and after.
     mode "dirichlet": A_s = Mhat_s^+ Mhat_s with every hop between different
-      blocks dropped (a cheaper operator that is not the paper's block)."""
+      blocks dropped (a cheaper operator that is not the paper's block).
+    mode "domain": A_s = P_s Mhat_Omega^+ Mhat_Omega P_s with Omega the block
+      widened by `pad` sites in the cut directions (domain_schur).  pad = 0 is
+      the Dirichlet block, pad = 2 reproduces the literal block (A reaches two
+      sites), and pad = 1 keeps only the paths that leave the block by one site."""
+    ids = block_ids(act, block)
     if mode == "dirichlet":
         return normal(act, U, p, block)
+    out = np.zeros_like(p)
+    if mode == "domain":
+        for k in range(int(ids.max()) + 1):
+            m = (ids == k)[None, ..., None, None]
+            om = domain_mask(act, block, k, pad)
+            y = domain_schur(act, U, m * p, om)
+            out += m * domain_schur(act, U, y, om, dagger=True)
+        return out
     if mode != "literal":
         raise ValueError(mode)
-    ids = block_ids(act, block)
-    out = np.zeros_like(p)
     for k in range(int(ids.max()) + 1):
         m = (ids == k)[None, ..., None, None]
         out += m * normal(act, U, m * p)
     return out
 
 
-def inner_block_cg(act: Action, U, r, block, l: int, mode: str = "literal") -> np.ndarray:
+def inner_block_cg(act: Action, U, r, block, l: int, mode: str = "literal",
+                   pad: int = 2) -> np.ndarray:
     """Sloppy preconditioner z = K_l^-1 r (Sec. 2.3 eqs. (4)-(5), "local iterations").
 
     For every block independently: l CG iterations on A_s z_s = r_s from z_s = 0
@@ -378,7 +440,7 @@ def inner_block_cg(act: Action, U, r, block, l: int, mode: str = "literal") -> n
     gam = _block_dot(rho, rho, ids, nblk).real
     active = gam > 0
     for _ in range(l):
-        w = block_precond_op(act, U, p, block, mode)
+        w = block_precond_op(act, U, p, block, mode, pad)
         pw = _block_dot(p, w, ids, nblk).real
         active &= pw > 0
         a = np.where(active, gam / np.where(active, pw, 1.0), 0.0)
@@ -393,13 +455,13 @@ def inner_block_cg(act: Action, U, r, block, l: int, mode: str = "literal") -> n
 
 
 def mspcg(act: Action, U, bhat, block, l: int, tol=1e-10, maxiter=10000, x0=None,
-          mode: str = "literal"):
+          mode: str = "literal", pad: int = 2):
     """Flexible preconditioned CG with K_l^-1 = inner_block_cg (Sec. 2.3).
 
     The preconditioner is inexact, so beta takes the flexible (Polak-Ribiere)
     form  beta = Re<z_new, r_new - r> / Re<z, r>.  Stop test as in cg()."""
     A = lambda v: normal(act, U, v)
-    K = lambda v: inner_block_cg(act, U, v, block, l, mode)
+    K = lambda v: inner_block_cg(act, U, v, block, l, mode, pad)
     bnorm = np.sqrt(norm2(bhat))
     info = SolveInfo()
     x = np.zeros_like(bhat) if x0 is None else x0.copy()
@@ -441,11 +503,13 @@ def mspcg(act: Action, U, bhat, block, l: int, tol=1e-10, maxiter=10000, x0=None
 def solve(act: Action, U, b, tol=1e-10, maxiter=10000, precond=None):
     """Full solution of D x = b through the even-odd normal equations.
 
-    precond = None: plain CG; precond = (block, l) or (block, l, mode): MSPCG."""
+    precond = None: plain CG; precond = (block, l), (block, l, mode) or
+    (block, l, "domain", pad): MSPCG."""
     _, bhat = prepare(act, U, b)
     if precond is None:
         xe, info = cg(act, U, bhat, tol, maxiter)
     else:
         mode = precond[2] if len(precond) > 2 else "literal"
-        xe, info = mspcg(act, U, bhat, precond[0], precond[1], tol, maxiter, mode=mode)
+        pad = precond[3] if len(precond) > 3 else 2
+        xe, info = mspcg(act, U, bhat, precond[0], precond[1], tol, maxiter, mode=mode, pad=pad)
     return reconstruct(act, U, b, xe), info

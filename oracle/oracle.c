@@ -130,6 +130,57 @@ static inline void coords_of(const int L[4], long lex, int c[4]) {
  * multiples of blk[mu]) than the output site.
  * only_sites != NULL: compute only those nsites output sites (all s) and
  * write them compactly as out[s][it][spin][colour]. */
+/* One term of the hop: acc += eta (1 - pm g_mu)-style spin matrix times the
+ * colour product of the link with the source spinor src[spin][colour]:
+ *   forward  (dir 0): chi = U_mu(x) src,       acc += eta (1 + pm g_mu) chi
+ *   backward (dir 1): chi = U_mu(x-mu)^+ src,  acc += eta (1 + pm g_mu) chi
+ * with pm = -sgn forward and +sgn backward (sgn = -1 for the dagger), so the
+ * forward term carries (1 - g_mu) and the backward one (1 + g_mu) for D_h. */
+static void hop_term(long V4, const cplx *U, long x, long y, int mu, int dir, double eta,
+                     double sgn, const cplx *src, cplx acc[4][3]) {
+    cplx chi[4][3];
+    if (dir == 0) {
+        const cplx *u = U + ((long)mu * V4 + x) * 9;
+        for (int sp = 0; sp < 4; ++sp)
+            for (int a = 0; a < 3; ++a) {
+                cplx t = 0;
+                for (int b = 0; b < 3; ++b) t += u[a * 3 + b] * src[sp * 3 + b];
+                chi[sp][a] = t;
+            }
+    } else {
+        const cplx *u = U + ((long)mu * V4 + y) * 9;
+        for (int sp = 0; sp < 4; ++sp)
+            for (int a = 0; a < 3; ++a) {
+                cplx t = 0;
+                for (int b = 0; b < 3; ++b) t += conj(u[b * 3 + a]) * src[sp * 3 + b];
+                chi[sp][a] = t;
+            }
+    }
+    const double pm = (dir == 0) ? -sgn : sgn;
+    for (int sp = 0; sp < 4; ++sp)
+        for (int a = 0; a < 3; ++a) {
+            cplx t = chi[sp][a];
+            for (int sq = 0; sq < 4; ++sq) t += pm * G[mu][sp][sq] * chi[sq][a];
+            acc[sp][a] += eta * t;
+        }
+}
+
+/* Neighbour of site c in direction mu (dir 0: +mu, 1: -mu) with the
+ * boundary sign eta; returns its lex index. */
+static long neighbour(const int L[4], int antiperiodic_t, const int c[4], int mu, int dir,
+                      int n[4], double *eta) {
+    n[0] = c[0]; n[1] = c[1]; n[2] = c[2]; n[3] = c[3];
+    *eta = 1.0;
+    if (dir == 0) {
+        n[mu] = c[mu] + 1;
+        if (n[mu] == L[mu]) { n[mu] = 0; if (mu == 3 && antiperiodic_t) *eta = -1.0; }
+    } else {
+        n[mu] = c[mu] - 1;
+        if (n[mu] < 0) { n[mu] = L[mu] - 1; if (mu == 3 && antiperiodic_t) *eta = -1.0; }
+    }
+    return lex_of(L, n);
+}
+
 static void hop_impl(const int L[4], int Ls, int antiperiodic_t, const int *blk,
                      const cplx *U, const cplx *in, cplx *out, int dagger,
                      const long *only_sites, long nsites) {
@@ -147,45 +198,11 @@ static void hop_impl(const int L[4], int Ls, int antiperiodic_t, const int *blk,
             memset(acc, 0, sizeof(acc));
             for (int mu = 0; mu < 4; ++mu) {
                 for (int dir = 0; dir < 2; ++dir) { /* 0: forward x+mu, 1: backward x-mu */
-                    int n[4] = {c[0], c[1], c[2], c[3]};
-                    double eta = 1.0;
-                    if (dir == 0) {
-                        n[mu] = c[mu] + 1;
-                        if (n[mu] == L[mu]) { n[mu] = 0; if (mu == 3 && antiperiodic_t) eta = -1.0; }
-                    } else {
-                        n[mu] = c[mu] - 1;
-                        if (n[mu] < 0) { n[mu] = L[mu] - 1; if (mu == 3 && antiperiodic_t) eta = -1.0; }
-                    }
+                    int n[4];
+                    double eta;
+                    const long y = neighbour(L, antiperiodic_t, c, mu, dir, n, &eta);
                     if (blk && (c[mu] / blk[mu]) != (n[mu] / blk[mu])) continue;
-                    const long y = lex_of(L, n);
-                    const cplx *src = in + ((long)s * V4 + y) * 12;
-                    /* colour multiply: chi = U_mu(x) src  or  U_mu(x-mu)^+ src */
-                    cplx chi[4][3];
-                    if (dir == 0) {
-                        const cplx *u = U + ((long)mu * V4 + x) * 9;
-                        for (int sp = 0; sp < 4; ++sp)
-                            for (int a = 0; a < 3; ++a) {
-                                cplx t = 0;
-                                for (int b = 0; b < 3; ++b) t += u[a * 3 + b] * src[sp * 3 + b];
-                                chi[sp][a] = t;
-                            }
-                    } else {
-                        const cplx *u = U + ((long)mu * V4 + y) * 9;
-                        for (int sp = 0; sp < 4; ++sp)
-                            for (int a = 0; a < 3; ++a) {
-                                cplx t = 0;
-                                for (int b = 0; b < 3; ++b) t += conj(u[b * 3 + a]) * src[sp * 3 + b];
-                                chi[sp][a] = t;
-                            }
-                    }
-                    /* spin matrix: (1 - sgn g_mu) forward, (1 + sgn g_mu) backward */
-                    const double pm = (dir == 0) ? -sgn : sgn;
-                    for (int sp = 0; sp < 4; ++sp)
-                        for (int a = 0; a < 3; ++a) {
-                            cplx t = chi[sp][a];
-                            for (int sq = 0; sq < 4; ++sq) t += pm * G[mu][sp][sq] * chi[sq][a];
-                            acc[sp][a] += eta * t;
-                        }
+                    hop_term(V4, U, x, y, mu, dir, eta, sgn, in + ((long)s * V4 + y) * 12, acc);
                 }
             }
             /* full mode: out[s][site]; site-list mode: compact out[s][it] */
@@ -279,6 +296,62 @@ void orc_dwf(const orc_action *a, const int *blk, const double *Ud, const double
         ktilde(V4, a->Ls, a->mf, in, k, 1);
 #pragma omp parallel for schedule(static)
         for (long i = 0; i < n; ++i) out[i] = a->b * t1[i] + a->c * t2[i] + in[i] - k[i];
+    }
+}
+
+/* (K psi)_s at one site y (the fifth-dimension hop of ktilde() above). */
+static void ktilde_site(long V4, int Ls, double mf, const cplx *in, long y, int s, cplx out[12]) {
+    int s_up = s - 1, s_dn = s + 1;
+    double f_up = 1.0, f_dn = 1.0;
+    if (s_up < 0) { s_up += Ls; f_up = -mf; }
+    if (s_dn >= Ls) { s_dn -= Ls; f_dn = -mf; }
+    const cplx *iu = in + ((long)s_up * V4 + y) * 12;
+    const cplx *id = in + ((long)s_dn * V4 + y) * 12;
+    for (int k = 0; k < 6; ++k) out[k] = f_up * iu[k];
+    for (int k = 6; k < 12; ++k) out[k] = f_dn * id[k];
+}
+
+/* D psi at the listed output sites only (every s), written compactly as
+ * out[s][it][spin][colour]; the same definition as orc_dwf,
+ *   (D psi)(x,s) = (4 - M5) (B psi)(x,s) - (D_h B psi)(x,s) / 2 + psi(x,s) - (K psi)(x,s),
+ * with B psi = b psi + c K psi formed only at x and its eight neighbours. */
+void orc_dwf_sites(const orc_action *a, const double *Ud, const double *ind, double *outd,
+                   const long *sites, long nsites) {
+    init_gamma();
+    const cplx *U = (const cplx *)Ud;
+    const cplx *in = (const cplx *)ind;
+    cplx *out = (cplx *)outd;
+    const int Ls = a->Ls;
+    const long V4 = (long)a->L[0] * a->L[1] * a->L[2] * a->L[3];
+    const double m4 = 4.0 - a->M5;
+#pragma omp parallel for schedule(static)
+    for (long it = 0; it < nsites; ++it) {
+        const long x = sites[it];
+        int c[4];
+        coords_of(a->L, x, c);
+        for (int s = 0; s < Ls; ++s) {
+            cplx acc[4][3];
+            memset(acc, 0, sizeof(acc));
+            cplx kb[12], bsrc[12];
+            for (int mu = 0; mu < 4; ++mu)
+                for (int dir = 0; dir < 2; ++dir) {
+                    int n[4];
+                    double eta;
+                    const long y = neighbour(a->L, a->antiperiodic_t, c, mu, dir, n, &eta);
+                    ktilde_site(V4, Ls, a->mf, in, y, s, kb);
+                    for (int k = 0; k < 12; ++k)
+                        bsrc[k] = a->b * in[((long)s * V4 + y) * 12 + k] + a->c * kb[k];
+                    hop_term(V4, U, x, y, mu, dir, eta, 1.0, bsrc, acc);
+                }
+            const cplx *ps = in + ((long)s * V4 + x) * 12;
+            ktilde_site(V4, Ls, a->mf, in, x, s, kb);
+            cplx *o = out + ((long)s * nsites + it) * 12;
+            const cplx *h = &acc[0][0];
+            for (int k = 0; k < 12; ++k) {
+                const cplx bx = a->b * ps[k] + a->c * kb[k];
+                o[k] = m4 * bx - 0.5 * h[k] + ps[k] - kb[k];
+            }
+        }
     }
 }
 

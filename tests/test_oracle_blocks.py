@@ -121,3 +121,67 @@ def test_mspcg_reaches_the_dense_solution(mode):
     assert relerr(x, x_ref) < 1e-9
     xc, infoc = O.solve(act, U, b, tol=1e-12)
     assert relerr(x, xc) < 1e-9
+
+
+def _dense_domain_block(D, even, blk_of, omega_site, k):
+    """Dense A_s of block k on the domain Omega: Schur complement of the
+    principal submatrix of D on Omega (over its odd sites), its normal matrix,
+    and the rows / columns of block k's even sites."""
+    om = np.broadcast_to(omega_site[None, ..., None, None], even.shape).ravel()
+    ev = even.ravel()
+    e, o = om & ev, om & ~ev
+    Mh = D[np.ix_(e, e)] - D[np.ix_(e, o)] @ np.linalg.solve(D[np.ix_(o, o)], D[np.ix_(o, e)])
+    AO = Mh.conj().T @ Mh
+    sel = (blk_of.ravel() == k)[np.flatnonzero(e)]
+    return AO[np.ix_(sel, sel)]
+
+
+@pytest.mark.parametrize("pad", [0, 1, 2])
+def test_padded_domain_block_is_schur_of_widened_principal_submatrix(pad):
+    """Block operator on the block widened by `pad` sites (Sec. 2.3 Fig. 3 read
+    on a padded domain): dense Schur complement of D's principal submatrix on
+    the widened block, normal matrix, restricted to the block."""
+    dims, Ls, blk = (8, 2, 2, 2), 2, (2, 2, 2, 2)
+    act, U, even, blk_of = _setup(dims, Ls, blk)
+    D = dense(lambda v: O.dwf(act, U, v), act.fshape)
+    Kp = dense(lambda v: O.block_precond_op(act, U, v, blk, "domain", pad), act.fshape, even)
+    ev_blk = blk_of[even]
+    for k in range(4):
+        om = O.domain_mask(act, blk, k, pad)
+        assert om.sum() == (2 + 2 * pad) * 8  # widened in x only
+        As = _dense_domain_block(D, even, blk_of, om, k)
+        sel = ev_blk == k
+        assert np.allclose(Kp[np.ix_(sel, sel)], As, rtol=0, atol=1e-13)
+        assert np.all(Kp[np.ix_(sel, ~sel)] == 0)
+    # HPD whenever Mhat_Omega is nonsingular
+    assert np.allclose(Kp, Kp.conj().T, atol=1e-13)
+    assert np.linalg.eigvalsh(Kp).min() > 0
+
+
+def test_padded_domain_limits():
+    """pad 0 is the Dirichlet block and pad 2 the literal block P_s A P_s (A
+    couples sites two hops apart, so a domain widened by two sites holds
+    every path that returns into the block); pad 1 lies strictly between."""
+    dims, Ls, blk = (8, 8, 4, 2), 4, (4, 2, 4, 2)
+    act, U, even, blk_of = _setup(dims, Ls, blk, seed=5)
+    p = O.parity_mask(act, synth.fermion_field(dims, Ls, 6), 0)
+    lit = O.block_precond_op(act, U, p, blk, "literal")
+    dir_ = O.block_precond_op(act, U, p, blk, "dirichlet")
+    d0 = O.block_precond_op(act, U, p, blk, "domain", 0)
+    d1 = O.block_precond_op(act, U, p, blk, "domain", 1)
+    d2 = O.block_precond_op(act, U, p, blk, "domain", 2)
+    assert relerr(d0, dir_) < 1e-14
+    assert relerr(d2, lit) < 1e-14
+    assert 1e-6 < relerr(d1, lit) < relerr(d0, lit)
+
+
+def test_domain_mask_wraps_periodically():
+    act = O.Action((8, 4, 4, 8), 2, 1.8, 0.1)
+    om = O.domain_mask(act, (4, 4, 4, 4), 0, 2)  # block at x, t in [0, 4)
+    x_in = om[0, 0, 0, :]
+    assert list(np.flatnonzero(x_in)) == [0, 1, 2, 3, 4, 5, 6, 7]
+    om1 = O.domain_mask(act, (4, 4, 4, 4), 1, 1)  # block at x in [4, 8), t in [0, 4)
+    assert list(np.flatnonzero(om1[0, 0, 0, :])) == [0, 3, 4, 5, 6, 7]
+    assert list(np.flatnonzero(om1[:, 0, 0, 4])) == [0, 1, 2, 3, 4, 7]
+    with pytest.raises(ValueError):
+        O.domain_mask(O.Action((4, 4, 4, 8), 2, 1.8, 0.1), (2, 4, 4, 4), 0, 2)

@@ -267,3 +267,15 @@ def test_cg_solution_matches_dense_direct_solve(p):
     kappa = np.linalg.cond(D)
     assert relerr(x, x_ref) < max(kappa, 10.0) ** 2 * 1e-12
     assert relerr(x, x_ref) < 1e-9
+
+
+@pytest.mark.parametrize("b,c", [(1.0, 0.0), (1.5, 0.5)])
+def test_dwf_sites_matches_full_operator(b, c):
+    """D psi on a list of sites equals those sites of the full D psi."""
+    dims, Ls = (4, 4, 2, 6), 6
+    act = O.Action(dims, Ls, 1.8, 0.05, b, c)
+    U = synth.gauge_field(dims, 0.3, 51)
+    psi = synth.fermion_field(dims, Ls, 52)
+    full = O.dwf(act, U, psi).reshape(Ls, act.V4, 4, 3)
+    sites = np.array([0, 3, 17, act.V4 - 1, 95, 40])
+    assert np.array_equal(O.dwf_sites(act, U, psi, sites), full[:, sites])
