@@ -107,14 +107,20 @@ enum {
     MSPCG_SOLVER_MSPCG = 2     /* FP64 flexible outer PCG, sloppy block preconditioner */
 };
 
-/* Block decomposition of the preconditioner.  block[mu] divides dims[mu] and
- * is even.  pad = depth of the padded domain on which each block's operator
- * is evaluated: pad >= 2 gives exactly the paper's A_s = P_s A P_s (Fig. 3:
- * the diagonal block of A, including the paths that leave the block and come
- * back); pad = 0 drops every hop between blocks (A_s = Mhat_s^+ Mhat_s with
- * a Dirichlet-cut Mhat_s); pad = 1 lies in between.  With FP16 local solves
- * one padded block must hold fewer than 2^24 sites per parity and under 4 GB
- * per FP16 field (MSPCG_EUNSUPPORTED otherwise). */
+/* Block decomposition of the preconditioner (Sec. 2.3, eq. (5), Fig. 3).
+ * block[mu] divides dims[mu] and is even.  Each block's operator is
+ * A_s = P_s Mhat_W^+ Mhat_W P_s, where W is the block widened by `pad` sites
+ * on both sides of every direction that holds more than one block, and
+ * Mhat_W is the even-odd Schur complement of the principal submatrix of D on
+ * W (every hop into or out of W dropped):
+ *   pad = 2: exactly the paper's A_s = P_s A P_s (the diagonal block of A,
+ *            including every path that leaves the block and comes back);
+ *   pad = 0: the Dirichlet-cut block Mhat_s^+ Mhat_s (no hop between blocks);
+ *   pad = 1: only the paths that leave the block by one site come back.
+ * In a cut direction dims[mu] - block[mu] >= 2 pad is required (the widened
+ * block must not wrap onto itself).  With FP16 local solves one widened
+ * block must hold fewer than 2^24 sites per parity and under 4 GB per FP16
+ * field (MSPCG_EUNSUPPORTED otherwise). */
 typedef struct {
     int block[4];
     int pad;
@@ -172,23 +178,48 @@ typedef struct {
     double kernel_ms[MSPCG_KC_COUNT];     /* timing = 1: summed kernel time per class */
     long kernel_launches[MSPCG_KC_COUNT];
     double kernel_bytes[MSPCG_KC_COUNT];  /* algorithmic bytes of those launches */
+    double* cg_coef;       /* caller buffer (may be NULL), plain CG only: (alpha_k, beta_k)
+                              per iteration k, 2 doubles each; the Lanczos tridiagonal
+                              they define bounds the spectrum of A from inside */
+    int cg_coef_cap;       /* iterations the buffer holds */
+    int cg_coef_len;
 } mspcg_solve_stats;
 
-/* Create a context on HIP device `device`.  Validates the action: every
- * extent even and >= 2, Ls compiled in, b != 0, finite parameters, and the
- * invertibility of M5op (1 + mf q^Ls != 0, q = -beta/alpha).  MSPCG_EINVAL
- * otherwise. */
+/* Warning bits reported by mspcg_get_warnings. */
+enum {
+    MSPCG_WARN_M5_RANGE = 1 /* M5 outside (0, 2): no wall-bound light mode */
+};
+
+/* Create a context for one DWF operator D_dw (Sec. 2.2: a Wilson operator
+ * with a large mass times a fictitious fifth dimension; the Moebius form of
+ * Sec. 1.1's "(generalized) domain wall fermion") on HIP device `device`.
+ * Validates the action: every extent even and >= 2, Ls compiled in, b != 0,
+ * finite parameters, and the invertibility of M5op (1 + mf q^Ls != 0,
+ * q = -beta/alpha); MSPCG_EINVAL otherwise.  M5 outside (0, 2) is accepted
+ * and flagged (mspcg_get_warnings).  *ctx receives the new context, which
+ * the caller releases with mspcg_destroy. */
 int mspcg_create(const mspcg_action* action, int device, mspcg_ctx** ctx);
 void mspcg_destroy(mspcg_ctx* ctx);
 const char* mspcg_strerror(int code);
 int mspcg_version(void);
+/* *warnings = the MSPCG_WARN_* bits of the context's action. */
+int mspcg_get_warnings(mspcg_ctx* ctx, int* warnings);
 
-/* Copy the gauge field (boundary layout, complex128 device pointer) into the
- * context's internal FP64/FP32/FP16 layouts, folding in the boundary sign. */
+/* Load the gauge field U_mu(x) of the sub-lattice the context holds (Sec. 1.1:
+ * gauge and pseudofermion fields are split into per-node sub-fields).  U_dev:
+ * complex128 device pointer in the gauge layout, read during the call (the
+ * caller keeps ownership); copied into the context's internal FP64/FP32/FP16
+ * link layouts with the time-boundary sign folded in.  Every call increments
+ * the context's gauge generation (mspcg_gauge_generation). */
 int mspcg_load_gauge(mspcg_ctx* ctx, const void* U_dev, hipStream_t stream);
+/* *gen = number of mspcg_load_gauge calls on this context so far. */
+int mspcg_gauge_generation(mspcg_ctx* ctx, unsigned long long* gen);
 
-/* out = op(in) in precision prec (FP64 or FP32; FP16 for MSPCG_OP_KBLOCK).
- * in/out: complex128 device pointers in the fermion layout, in != out.
+/* out = op(in) in precision prec (FP64 or FP32; FP16 for MSPCG_OP_KBLOCK):
+ * the operators of Sec. 2.2 (D_dw, its adjoint, the normal operator of
+ * eq. (3) in even-odd Schur form) and the block preconditioner of Sec. 2.3
+ * eq. (5).  in/out: complex128 device pointers in the fermion layout,
+ * in != out, both caller-owned; asynchronous on `stream`.
  * MSPCG_OP_KBLOCK uses the blocking set by mspcg_set_blocking. */
 int mspcg_apply(mspcg_ctx* ctx, int op, int prec, const void* in_dev, void* out_dev,
                 hipStream_t stream);
@@ -201,15 +232,35 @@ int mspcg_set_blocking(mspcg_ctx* ctx, const mspcg_blocking* blocking);
 int mspcg_precond(mspcg_ctx* ctx, int inner_iters, int prec, const void* r_dev, void* z_dev,
                   hipStream_t stream);
 
-/* Solve D x = b (b, x: full fields, complex128).  The even part is solved on
- * A = Mhat^+ Mhat and the odd part reconstructed.  On MSPCG_ENOCONV x holds
- * the last iterate and stats are filled.  stats may be NULL. */
+/* Solve D_dw x = b through the normal equations (Sec. 2.2, eq. (3)) in
+ * even-odd Schur form: CG (or mixed-precision CG) on A = Mhat^+ Mhat, or
+ * the multisplitting-preconditioned CG of Sec. 2.3 (flexible outer PCG with
+ * z = K_l^-1 r, eqs. (4)-(5)).  b, x: full fields, complex128 device
+ * pointers, caller-owned, b != x (x is read as the initial guess when
+ * params->use_x0).  The even part is solved and the odd part reconstructed.
+ * Returns after the stream has completed.  On MSPCG_ENOCONV x holds the
+ * last iterate and stats are filled.  stats may be NULL. */
 int mspcg_solve(mspcg_ctx* ctx, const void* b_dev, void* x_dev, const mspcg_solve_params* params,
                 mspcg_solve_stats* stats, hipStream_t stream);
 
+/* Pseudofermion action of HMC ensemble generation (Sec. 1.1: the Dirac
+ * inversion that dominates the cost): solves A X = phi (even fields, as
+ * params->rhs_normal = 1) and returns S = phi^+ A^-1 phi = Re <phi, X> in
+ * FP64 (fixed-order reduction).  dphi (may be NULL) receives 2 X, the
+ * gradient of S with respect to phi in the convention dS = Re sum conj(dphi)
+ * d(phi).  phi, X, dphi: distinct complex128 device pointers in the fermion
+ * layout, caller-owned.  Returns after the stream has completed; S is
+ * written also on MSPCG_ENOCONV. */
+int mspcg_pseudofermion_action(mspcg_ctx* ctx, const void* phi_dev, void* X_dev, void* dphi_dev,
+                               const mspcg_solve_params* params, double* S,
+                               mspcg_solve_stats* stats, hipStream_t stream);
+
 /* Solve n independent systems (one context each, possibly of different sizes)
- * with the same parameters; the outer iterations of all still-active systems
- * are interleaved on one stream.  stats: array of n (may be NULL). */
+ * with the same parameters: the paper's several nodes each solving their own
+ * sub-problem (Sec. 2.1, Fig. 1), here several lattices sharing one GPU.  The
+ * outer iterations of all still-active systems are interleaved on one
+ * stream; arguments as for mspcg_solve, per system.  stats: array of n (may
+ * be NULL). */
 int mspcg_solve_batch(mspcg_ctx* const* ctxs, int n, const void* const* b_dev, void* const* x_dev,
                       const mspcg_solve_params* params, mspcg_solve_stats* stats,
                       hipStream_t stream);

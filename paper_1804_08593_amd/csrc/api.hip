@@ -419,6 +419,11 @@ extern "C" int mspcg_create(const mspcg_action* a, int device, mspcg_ctx** out) 
     c->L32 = nullptr;
     c->L16 = nullptr;
     c->gauge = false;
+    c->gauge_gen = 0;
+    // the domain-wall construction needs a negative Wilson mass -M5 in
+    // (-2, 0) for one light mode bound to the walls; other values are
+    // accepted and flagged
+    c->warnings = (a->M5 > 0.0 && a->M5 < 2.0) ? 0 : MSPCG_WARN_M5_RANGE;
     c->partials = nullptr;
     c->partials_len = 0;
     c->has_blocking = false;
@@ -484,7 +489,20 @@ extern "C" int mspcg_load_gauge(mspcg_ctx* c, const void* U_dev, hipStream_t st)
     if ((e = launch_pack_links<F16>(c->U, c->L16, c->L, c->L, one, c->lat, c->act.antiperiodic_t, st)))
         return MSPCG_EHIP;
     c->gauge = true;
+    ++c->gauge_gen;
     c->dom.built = false;  // domain links depend on the gauge field
+    return MSPCG_OK;
+}
+
+extern "C" int mspcg_gauge_generation(mspcg_ctx* c, unsigned long long* gen) {
+    if (!c || !gen) return MSPCG_EINVAL;
+    *gen = c->gauge_gen;
+    return MSPCG_OK;
+}
+
+extern "C" int mspcg_get_warnings(mspcg_ctx* c, int* warnings) {
+    if (!c || !warnings) return MSPCG_EINVAL;
+    *warnings = c->warnings;
     return MSPCG_OK;
 }
 
@@ -654,6 +672,38 @@ extern "C" int mspcg_solve(mspcg_ctx* c, const void* b_dev, void* x_dev,
     if (!c->gauge) return MSPCG_ENOGAUGE;
     MSPCG_HIP(hipSetDevice(c->device));
     return solve_one(c, b_dev, x_dev, p, stats, st);
+}
+
+extern "C" int mspcg_pseudofermion_action(mspcg_ctx* c, const void* phi_dev, void* X_dev,
+                                          void* dphi_dev, const mspcg_solve_params* p,
+                                          double* S, mspcg_solve_stats* stats, hipStream_t st) {
+    if (!c || !phi_dev || !X_dev || !p || !S || phi_dev == X_dev || dphi_dev == phi_dev ||
+        dphi_dev == X_dev)
+        return MSPCG_EINVAL;
+    if (!c->gauge) return MSPCG_ENOGAUGE;
+    MSPCG_HIP(hipSetDevice(c->device));
+    mspcg_solve_params q = *p;
+    q.rhs_normal = 1;
+    const int rc = solve_one(c, phi_dev, X_dev, &q, stats, st);
+    if (rc != MSPCG_OK && rc != MSPCG_ENOCONV) return rc;
+    // S = Re <phi, X> over the full-layout even fields (odd sites are zero
+    // in X), fixed-order partial sums
+    const long N = c->V4 * c->Ls;  // 5D entries of 12 complex values
+    const long np = blas_grid_x(12 * N);
+    int e = ensure_partials(c, (size_t)(2 * np + 16));
+    if (e) return e;
+    double* part = c->partials;
+    if (launch_dot2((const double2*)phi_dev, (const double2*)X_dev, (const double2*)X_dev, N, part,
+                    np, st))
+        return MSPCG_EHIP;
+    if (launch_reduce_sum(part, (int)np, part + 2 * np, st)) return MSPCG_EHIP;
+    if (dphi_dev && launch_scale((double2*)dphi_dev, (const double2*)X_dev, 2.0, 12 * N, st))
+        return MSPCG_EHIP;
+    double v = 0;
+    MSPCG_HIP(hipMemcpyAsync(&v, part + 2 * np, sizeof(double), hipMemcpyDeviceToHost, st));
+    MSPCG_HIP(hipStreamSynchronize(st));
+    *S = v;
+    return rc;
 }
 
 extern "C" int mspcg_solve_batch(mspcg_ctx* const* ctxs, int n, const void* const* b_dev,

@@ -170,7 +170,13 @@ __global__ void cg_beta_kernel(DevScalars* sc, const double* partials, int npart
         sc->beta = rr / sc->rr;
         sc->rr = rr;
         const int k = sc->iter;
-        if (hist && k < hist_cap) hist[k] = rr;
+        // per iteration: |r|^2 and the CG coefficients alpha, beta (their
+        // Lanczos tridiagonal estimates the spectrum of A)
+        if (hist && k < hist_cap) {
+            hist[3 * k] = rr;
+            hist[3 * k + 1] = sc->alpha;
+            hist[3 * k + 2] = sc->beta;
+        }
         sc->iter = k + 1;
         if (!isfinite(rr)) {
             sc->breakdown = 1;
@@ -247,9 +253,23 @@ __global__ void zero_kernel(double2* y, long n) {
         y[i] = make_double2(0.0, 0.0);
 }
 
+__global__ void scale_kernel(double2* y, const double2* x, double a, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        const double2 v = x[i];
+        y[i] = make_double2(a * v.x, a * v.y);
+    }
+}
+
 int last_error() { return hipGetLastError() == hipSuccess ? 0 : -2; }
 
 }  // namespace
+
+int launch_scale(double2* y, const double2* x, double a, long n, hipStream_t st) {
+    hipLaunchKernelGGL(scale_kernel, dim3((unsigned)blas_grid_x(n)), dim3(kThreads), 0, st, y, x,
+                       a, n);
+    return last_error();
+}
 
 int launch_zero(double2* y, long N, hipStream_t st) {
     hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blas_grid_x(12 * N)), dim3(kThreads), 0, st, y,

@@ -79,6 +79,8 @@ struct mspcg_ctx {
     float2* L32;
     __half2* L16;
     bool gauge;
+    unsigned long long gauge_gen;  // incremented by every mspcg_load_gauge
+    int warnings;                  // MSPCG_WARN_* bits found by mspcg_create
     // buffers
     std::map<std::string, std::pair<void*, size_t>> bufs;
     double* partials;

@@ -160,6 +160,8 @@ int launch_copy_norm(double2* dst, const double2* src, long N, double* partials,
 int launch_dot2(const double2* z, const double2* r, const double2* q, long N, double* partials,
                 long nparts, hipStream_t st);
 int launch_zero(double2* y, long N, hipStream_t st);
+// y = a x on n complex values (any layout)
+int launch_scale(double2* y, const double2* x, double a, long n, hipStream_t st);
 
 // FP32 iterations of the mixed-precision CG
 int launch_accum32(double2* x, float2* xs, long N, int Ls, hipStream_t st);

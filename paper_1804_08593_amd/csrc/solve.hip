@@ -81,7 +81,8 @@ int ensure_hist(mspcg_ctx* c, int cap) {
     if (c->hist) (void)hipFree(c->hist);
     c->hist = nullptr;
     c->hist_cap = 0;
-    if (hipMalloc(&c->hist, (size_t)cap * sizeof(double)) != hipSuccess) return MSPCG_ENOMEM;
+    // three entries per iteration: |r|^2, alpha, beta
+    if (hipMalloc(&c->hist, (size_t)cap * 3 * sizeof(double)) != hipSuccess) return MSPCG_ENOMEM;
     c->hist_cap = cap;
     return 0;
 }
@@ -114,15 +115,26 @@ struct Solver {
         st->converged = converged ? 1 : 0;
         st->true_rel_resid = sqrt(true_rr / bb);
         st->resid_history_len = 0;
-        if (st->resid_history && st->resid_history_cap > 0 && c->hist) {
-            const int n = iters < st->resid_history_cap ? iters : st->resid_history_cap;
-            if (n > 0) {
-                std::vector<double> h(n);
-                if (hipMemcpy(h.data(), c->hist, n * sizeof(double), hipMemcpyDeviceToHost) ==
-                    hipSuccess) {
-                    for (int i = 0; i < n; ++i) st->resid_history[i] = sqrt(h[i] / bb);
-                    st->resid_history_len = n;
+        st->cg_coef_len = 0;
+        const bool want_h = st->resid_history && st->resid_history_cap > 0;
+        const bool want_c = st->cg_coef && st->cg_coef_cap > 0 && p->solver == MSPCG_SOLVER_CG;
+        const int cap_h = want_h ? st->resid_history_cap : 0;
+        const int cap_c = want_c ? st->cg_coef_cap : 0;
+        int n = cap_h > cap_c ? cap_h : cap_c;
+        if (iters < n) n = iters;
+        if (n > 0 && c->hist) {
+            std::vector<double> h(3 * (size_t)n);
+            if (hipMemcpy(h.data(), c->hist, h.size() * sizeof(double), hipMemcpyDeviceToHost) ==
+                hipSuccess) {
+                const int nh = n < cap_h ? n : cap_h;
+                for (int i = 0; i < nh; ++i) st->resid_history[i] = sqrt(h[3 * i] / bb);
+                st->resid_history_len = nh;
+                const int nc = n < cap_c ? n : cap_c;
+                for (int i = 0; i < nc; ++i) {
+                    st->cg_coef[2 * i] = h[3 * i + 1];
+                    st->cg_coef[2 * i + 1] = h[3 * i + 2];
                 }
+                st->cg_coef_len = nc;
             }
         }
     }
@@ -494,6 +506,7 @@ void zero_stats(mspcg_solve_stats* st) {
     st->converged = 1;
     st->true_rel_resid = 0.0;
     st->resid_history_len = 0;
+    st->cg_coef_len = 0;
 }
 
 void clear_timing(mspcg_solve_stats* st) {

@@ -25,7 +25,9 @@ KC_COUNT = 7
 EXPORTS = ("mspcg_create", "mspcg_destroy", "mspcg_strerror", "mspcg_version",
            "mspcg_load_gauge", "mspcg_apply", "mspcg_set_blocking", "mspcg_precond",
            "mspcg_solve", "mspcg_solve_batch", "mspcg_force", "mspcg_get_tuning",
-           "mspcg_set_tuning", "mspcg_autotune", "mspcg_tune_blocking")
+           "mspcg_set_tuning", "mspcg_autotune", "mspcg_tune_blocking",
+           "mspcg_get_warnings", "mspcg_gauge_generation", "mspcg_pseudofermion_action")
+WARN_M5_RANGE = 1
 
 
 class MspcgError(RuntimeError):
@@ -68,7 +70,9 @@ class SolveStats(ctypes.Structure):
                 ("resid_history_cap", ctypes.c_int), ("resid_history_len", ctypes.c_int),
                 ("kernel_ms", ctypes.c_double * KC_COUNT),
                 ("kernel_launches", ctypes.c_long * KC_COUNT),
-                ("kernel_bytes", ctypes.c_double * KC_COUNT)]
+                ("kernel_bytes", ctypes.c_double * KC_COUNT),
+                ("cg_coef", ctypes.POINTER(ctypes.c_double)),
+                ("cg_coef_cap", ctypes.c_int), ("cg_coef_len", ctypes.c_int)]
 
 
 _lib = None
@@ -103,6 +107,11 @@ def load(path: str = LIB_PATH):
                                           ctypes.POINTER(P), ctypes.POINTER(SolveParams),
                                           ctypes.POINTER(SolveStats), P]
         lib.mspcg_force.argtypes = [P, P, P, P, P, P]
+        lib.mspcg_get_warnings.argtypes = [P, ctypes.POINTER(I)]
+        lib.mspcg_gauge_generation.argtypes = [P, ctypes.POINTER(ctypes.c_ulonglong)]
+        lib.mspcg_pseudofermion_action.argtypes = [P, P, P, P, ctypes.POINTER(SolveParams),
+                                                   ctypes.POINTER(ctypes.c_double),
+                                                   ctypes.POINTER(SolveStats), P]
         lib.mspcg_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
         lib.mspcg_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
         lib.mspcg_autotune.argtypes = [P, ctypes.POINTER(Blocking), ctypes.c_char_p, P]
@@ -165,6 +174,19 @@ class Context:
         self._h = h
         self.dims = tuple(int(x) for x in dims)
         self.Ls = int(Ls)
+        w = ctypes.c_int()
+        _check(lib.mspcg_get_warnings(h, ctypes.byref(w)), "mspcg_get_warnings")
+        self.warnings = w.value
+        if w.value & WARN_M5_RANGE:
+            import warnings
+            warnings.warn(f"M5 = {M5} lies outside (0, 2): the operator has no wall-bound "
+                          "light mode", RuntimeWarning, stacklevel=2)
+
+    @property
+    def gauge_generation(self) -> int:
+        g = ctypes.c_ulonglong()
+        _check(load().mspcg_gauge_generation(self._h, ctypes.byref(g)), "mspcg_gauge_generation")
+        return g.value
 
     @property
     def handle(self):
@@ -211,17 +233,36 @@ class Context:
                                     _stream(stream)), "mspcg_precond")
         return z
 
-    def solve(self, b, x, params: SolveParams, history=0, stream=None, allow_noconv=False):
+    def solve(self, b, x, params: SolveParams, history=0, stream=None, allow_noconv=False,
+              coef=0):
+        """history / coef: iterations of residual history / plain-CG coefficients to return."""
         st = SolveStats()
-        hist = None
+        hist = cf = None
         if history:
             hist = (ctypes.c_double * int(history))()
             st.resid_history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
             st.resid_history_cap = int(history)
+        if coef:
+            cf = (ctypes.c_double * (2 * int(coef)))()
+            st.cg_coef = ctypes.cast(cf, ctypes.POINTER(ctypes.c_double))
+            st.cg_coef_cap = int(coef)
         rc = load().mspcg_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(params),
                                 ctypes.byref(st), _stream(stream))
         _check(rc, "mspcg_solve", allow=(ENOCONV,) if allow_noconv else ())
-        return stats_dict(st, hist, rc)
+        return stats_dict(st, hist, rc, cf)
+
+    def pseudofermion_action(self, phi, X, dphi=None, params: SolveParams = None, stream=None,
+                             allow_noconv=False):
+        """S = phi^+ A^-1 phi; X receives A^-1 phi, dphi (optional) 2 X."""
+        p = params if params is not None else make_params(tol=1e-12, maxiter=20000)
+        S = ctypes.c_double()
+        st = SolveStats()
+        rc = load().mspcg_pseudofermion_action(self._h, _ptr(phi), _ptr(X),
+                                               _ptr(dphi) if dphi is not None else None,
+                                               ctypes.byref(p), ctypes.byref(S),
+                                               ctypes.byref(st), _stream(stream))
+        _check(rc, "mspcg_pseudofermion_action", allow=(ENOCONV,) if allow_noconv else ())
+        return S.value, stats_dict(st, None, rc)
 
     def get_tuning(self) -> Tuning:
         t = Tuning()
@@ -265,7 +306,7 @@ class Context:
         return F, G
 
 
-def stats_dict(st: SolveStats, hist=None, rc=OK) -> dict:
+def stats_dict(st: SolveStats, hist=None, rc=OK, coef=None) -> dict:
     d = {
         "rc": rc,
         "outer_iters": st.outer_iters,
@@ -280,6 +321,8 @@ def stats_dict(st: SolveStats, hist=None, rc=OK) -> dict:
     }
     if hist is not None:
         d["history"] = np.array(hist[:st.resid_history_len])
+    if coef is not None:
+        d["cg_coef"] = np.array(coef[:2 * st.cg_coef_len]).reshape(-1, 2)
     return d
 
 

@@ -64,3 +64,21 @@ def parity(dims):
 
 def relerr(a, b):
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def lanczos_kappa(coef):
+    """Condition-number estimate from CG coefficients (alpha_k, beta_k): the
+    extreme eigenvalues of the Lanczos tridiagonal T with
+      T[j, j] = 1/alpha_j + beta_{j-1}/alpha_{j-1},  T[j, j+1] = sqrt(beta_j)/alpha_j
+    (Ritz values of A on the Krylov space, so lmin(T) >= lmin(A) and
+    lmax(T) <= lmax(A)).  Returns (kappa, lmin, lmax)."""
+    coef = np.asarray(coef, dtype=float)
+    a, b = coef[:, 0], coef[:, 1]
+    n = len(a)
+    T = np.zeros((n, n))
+    for j in range(n):
+        T[j, j] = 1.0 / a[j] + (b[j - 1] / a[j - 1] if j > 0 else 0.0)
+        if j + 1 < n:
+            T[j, j + 1] = T[j + 1, j] = np.sqrt(b[j]) / a[j]
+    ev = np.linalg.eigvalsh(T)
+    return ev[-1] / ev[0], ev[0], ev[-1]

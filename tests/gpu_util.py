@@ -30,3 +30,27 @@ def relerr(a, b) -> float:
 
 def say(*args):
     print(*args, flush=True)
+
+
+def site_err(a, b) -> float:
+    """Largest error of one 5D entry (x, s): max over entries of
+    |a_e - b_e| / max(|b_e|, rms_b), with |.| the 2-norm of the entry's 12
+    complex components and rms_b the root mean square of b's nonzero entry
+    norms.  A wrong or missing contribution at a few sites shows up here even
+    when the field's global relative error stays small."""
+    d = np.linalg.norm((a - b).reshape(-1, 12), axis=1)
+    nb = np.linalg.norm(b.reshape(-1, 12), axis=1)
+    nz = nb > 0
+    rms = np.sqrt(np.mean(nb[nz] ** 2)) if nz.any() else 1.0
+    return float(np.max(d / np.maximum(nb, rms)))
+
+
+# FP16 storage rounds a stored value v / m (m: max |real| of its 5D entry, so
+# |v / m| <= 1) to 11 significant bits: at most 2^-12 of m per component.
+# Bars below charge one such unit per stored rounding on the dependency
+# chain of the result (first-order, linear accumulation).
+FP16_UNIT = 2.0 ** -12
+
+
+def fp16_bar(n_roundings: int) -> float:
+    return n_roundings * FP16_UNIT

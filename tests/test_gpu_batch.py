@@ -8,6 +8,7 @@ import torch
 
 import oracle as O
 from paper_1804_08593_amd import mspcg, synth
+from tests._util import lanczos_kappa
 from tests.gpu_util import dev, host, relerr, say
 
 pytestmark = pytest.mark.gpu
@@ -40,6 +41,13 @@ def test_batch_equals_individual_solves(solver):
         ref.append((x.clone(), st))
     # one batched, graph-replayed solve (run twice: replays of a fresh graph
     # after eager work in between must give the same answer)
+    # the eager solutions against the oracle's solution at 1e-13
+    for (ctx, U, b), (xr, sr), (d, Ls, mf, blk) in zip(sys, ref, SMALL):
+        act = O.Action(d, Ls, 1.8, mf, 1.5, 0.5)
+        x_or, _ = O.solve(act, U, host(b), tol=1e-13)
+        err = relerr(host(xr), x_or)
+        say(f"system {d} Ls={Ls}: |x - x_oracle| / |x_oracle| = {err:.2e}")
+        assert err <= 1e-8
     for rep in range(2):
         xs = [torch.zeros_like(b) for _, _, b in sys]
         sts = mspcg.solve_batch([c for c, _, _ in sys], [b for _, _, b in sys], xs, prm,
@@ -57,36 +65,66 @@ def test_batch_equals_individual_solves(solver):
         torch.cuda.synchronize()
 
 
-def test_config4_six_uneven_lattices():
+C4_SHAPES = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 16), (12, 12, 12, 24),
+             (16, 16, 16, 32), (20, 20, 20, 20)]
+C4_LSMF = [(8, 0.05), (12, 0.01), (16, 0.05), (8, 0.01), (12, 0.05), (16, 0.01)]
+
+
+@pytest.fixture(scope="module")
+def c4():
     """8^4, 12^4, 16^4, 12^3x24, 16^3x32, 20^4 Moebius lattices with
     (Ls, mf) = (8,.05) (12,.01) (16,.05) (8,.01) (12,.05) (16,.01), links
     exp(0.25 i H), autotuned blocking, one batched MSPCG solve to 1e-10."""
-    shapes = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 16), (12, 12, 12, 24),
-              (16, 16, 16, 32), (20, 20, 20, 20)]
-    lsmf = [(8, 0.05), (12, 0.01), (16, 0.05), (8, 0.01), (12, 0.05), (16, 0.01)]
     sys = []
     base = mspcg.make_params(tol=1e-10, maxiter=3000, solver=mspcg.SOLVER_MSPCG, inner_iters=6,
                              inner_prec=mspcg.FP16, block=(0, 0, 0, 0))
-    for i, (d, (Ls, mf)) in enumerate(zip(shapes, lsmf)):
+    for i, (d, (Ls, mf)) in enumerate(zip(C4_SHAPES, C4_LSMF)):
         ctx, U, b = _make(d, Ls, mf, 0.25, 1040 + i, 2040 + i)
         blk = ctx.tune_blocking(base, probe_iters=6)
         say(f"lattice {d} Ls={Ls}: tuned blocking {blk}")
-        sys.append((ctx, U, b))
-    xs = [torch.zeros_like(b) for _, _, b in sys]
-    sts = mspcg.solve_batch([c for c, _, _ in sys], [b for _, _, b in sys], xs, base)
-    for (ctx, U, b), x, st in zip(sys, xs, sts):
+        sys.append((ctx, U, b, mf))
+    xs = [torch.zeros_like(b) for _, _, b, _ in sys]
+    sts = mspcg.solve_batch([c for c, _, _, _ in sys], [b for _, _, b, _ in sys], xs, base)
+    return sys, xs, sts
+
+
+def test_config4_six_uneven_lattices(c4):
+    sys, xs, sts = c4
+    for (ctx, U, b, mf), x, st in zip(sys, xs, sts):
         say(f"  {ctx.dims} Ls={ctx.Ls}: outer {st['outer_iters']} resid {st['true_rel_resid']:.2e}")
         assert st["converged"] and st["true_rel_resid"] <= 1e-10
-        # re-measure the full-system residual |D x - b| / |b| with the GPU operator
-        dx = torch.zeros_like(b)
-        ctx.apply(mspcg.OP_D, x, dx)
-        r = (torch.linalg.vector_norm(dx - b) / torch.linalg.vector_norm(b)).item()
-        assert r <= 1e-8
-    # the smallest lattice also against the oracle's operator
-    ctx, U, b = sys[0]
-    act = O.Action(ctx.dims, ctx.Ls, 1.8, 0.05, 1.5, 0.5)
+
+
+@pytest.mark.parametrize("i", range(len(C4_SHAPES)))
+def test_config4_lattice_against_oracle(c4, i):
+    """Every batched lattice: the Schur residual of its x re-measured by the
+    oracle, the full-system residual |D x - b| on sampled sites by the
+    oracle, and the distance to an FP64 CG solution at 1e-12 within the
+    kappa-qualified bound kappa (r_1 + r_2) (kappa from that CG's Lanczos
+    coefficients, r the oracle-measured relative residuals)."""
+    sys, xs, sts = c4
+    ctx, U, b, mf = sys[i]
+    x = xs[i]
+    act = O.Action(ctx.dims, ctx.Ls, 1.8, mf, 1.5, 0.5)
     bh = host(b)
     _, bhat = O.prepare(act, U, bh)
-    xe = O.parity_mask(act, host(xs[0]), 0)
-    rr = np.sqrt(O.norm2(bhat - O.normal(act, U, xe)) / O.norm2(bhat))
-    assert rr <= 1e-10
+    nb = np.sqrt(O.norm2(bhat))
+    xe = O.parity_mask(act, host(x), 0)
+    r_b = np.sqrt(O.norm2(bhat - O.normal(act, U, xe))) / nb
+    xc = torch.zeros_like(b)
+    sc = ctx.solve(b, xc, mspcg.make_params(tol=1e-12, maxiter=5000, solver=mspcg.SOLVER_CG),
+                   coef=5000)
+    kappa, lo, hi = lanczos_kappa(sc["cg_coef"])
+    xce = O.parity_mask(act, host(xc), 0)
+    r_c = np.sqrt(O.norm2(bhat - O.normal(act, U, xce))) / nb
+    err = relerr(xe, xce)
+    rng = np.random.default_rng(100 + i)
+    sites = np.sort(rng.choice(act.V4, size=min(500, act.V4), replace=False))
+    dx = O.dwf_sites(act, U, host(x), sites)
+    bs = bh.reshape(act.Ls, act.V4, 4, 3)[:, sites]
+    r_full = relerr(dx, bs)
+    say(f"  {ctx.dims} Ls={ctx.Ls}: oracle resid {r_b:.2e} (CG {r_c:.2e}), kappa {kappa:.3g}, "
+        f"|x - x_cg|/|x| {err:.2e} <= {kappa * (r_b + r_c):.2e}, sampled |Dx-b|/|b| {r_full:.2e}")
+    assert r_b <= 1e-10 * 1.01 and r_c <= 1e-12 * 1.01
+    assert err <= kappa * (r_b + r_c)
+    assert r_full <= 1e-8

@@ -163,3 +163,55 @@ def test_autograd_function():
     Sref = O.dot(O.parity_mask(act, host(phi.detach()), 0),
                  O.cg(act, U, host(phi.detach()), tol=1e-13)[0]).real
     assert abs(S.item() - Sref) <= 1e-10 * abs(Sref)
+
+
+def test_autograd_backward_uses_its_own_links():
+    """Two forward passes with different links on one context, then the
+    backward of the first: its gradient must be that of the first links."""
+    dims, Ls = (4, 4, 2, 4), 8
+    act, U1, ctx = setup(dims, Ls, MOB["M5"], 0.05, MOB["b"], MOB["c"], eps=0.25, gseed=48)
+    U2 = synth.gauge_field(dims, 0.25, 49)
+    eta = O.parity_mask(act, synth.fermion_field(dims, Ls, 50), 0)
+    phi = dev(O.schur(act, U1, eta, dagger=True)).requires_grad_(True)
+    Ut1 = dev(U1).requires_grad_(True)
+    Ut2 = dev(U2).requires_grad_(True)
+    S1 = pseudofermion_action(Ut1, phi, ctx)
+    S2 = pseudofermion_action(Ut2, phi, ctx)
+    assert abs(S1.item() - S2.item()) > 1e-6 * abs(S1.item())
+    S1.backward()
+    g1 = Ut1.grad.clone()
+    # reference: a fresh context that only ever saw U1
+    ctx_ref = mspcg.Context(dims, Ls, MOB["M5"], 0.05, MOB["b"], MOB["c"])
+    Ur = dev(U1).requires_grad_(True)
+    pseudofermion_action(Ur, phi.detach(), ctx_ref).backward()
+    err = relerr(host(g1), host(Ur.grad))
+    say(f"backward after a second forward: relerr vs fresh context {err:.2e}")
+    assert err <= 1e-12
+
+
+def test_pseudofermion_action_entry():
+    """mspcg_pseudofermion_action: S = Re<phi, A^-1 phi> against the oracle,
+    dphi = 2 X, X = A^-1 phi."""
+    dims, Ls = (4, 4, 4, 4), 8
+    act, U, ctx = setup(dims, Ls, MOB["M5"], 0.05, MOB["b"], MOB["c"], eps=0.25, gseed=51)
+    eta = O.parity_mask(act, synth.fermion_field(dims, Ls, 52), 0)
+    phih = O.schur(act, U, eta, dagger=True)
+    phi = dev(phih)
+    X = torch.zeros_like(phi)
+    dphi = torch.zeros_like(phi)
+    S, st = ctx.pseudofermion_action(phi, X, dphi, mspcg.make_params(tol=1e-12, maxiter=5000))
+    assert st["converged"]
+    Xo, _ = O.cg(act, U, phih, tol=1e-13)
+    Sref = O.dot(phih, Xo).real
+    say(f"S = {S:.12e} oracle {Sref:.12e}")
+    assert abs(S - Sref) <= 1e-10 * abs(Sref)
+    assert relerr(host(X), Xo) <= 1e-9
+    assert torch.equal(dphi, 2.0 * X)
+
+
+def test_m5_range_warning():
+    with pytest.warns(RuntimeWarning):
+        c = mspcg.Context((4, 4, 4, 4), 4, 2.5, 0.1)
+    assert c.warnings & mspcg.WARN_M5_RANGE
+    c2 = mspcg.Context((4, 4, 4, 4), 4, 1.8, 0.1)
+    assert c2.warnings == 0

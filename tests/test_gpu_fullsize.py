@@ -12,6 +12,7 @@ import torch
 
 import oracle as O
 from paper_1804_08593_amd import mspcg, synth
+from tests._util import lanczos_kappa
 from tests.gpu_util import dev, host, relerr, say, setup
 
 pytestmark = pytest.mark.gpu
@@ -53,19 +54,30 @@ def test_c3_mspcg_and_cg_solves(c3):
                                              block=C3["block"], pad=2, inner_iters=6,
                                              inner_prec=mspcg.FP16))
     xc = torch.zeros_like(bd)
-    sc = ctx.solve(bd, xc, mspcg.make_params(tol=1e-12, solver=mspcg.SOLVER_CG))
+    sc = ctx.solve(bd, xc, mspcg.make_params(tol=1e-12, solver=mspcg.SOLVER_CG), coef=5000)
     say(f"  MSPCG {sm['outer_iters']} it, CG(1e-12) {sc['outer_iters']} it")
     assert sm["converged"] and sc["converged"]
     assert sm["outer_iters"] < sc["outer_iters"]
     _, bhat = O.prepare(act, U, b)
     nb = np.sqrt(O.norm2(bhat))
+    res, xev = [], []
     for x, tol in ((xm, 1e-10), (xc, 1e-12)):
-        r = bhat - O.normal(act, U, O.parity_mask(act, host(x), 0))
+        xe = O.parity_mask(act, host(x), 0)
+        r = bhat - O.normal(act, U, xe)
         rel = np.sqrt(O.norm2(r)) / nb
         say(f"  oracle true residual {rel:.2e}")
         assert rel <= tol * 1.01
+        res.append(rel)
+        xev.append(xe)
+    # solution error qualified by the condition number (kappa from the CG's
+    # Lanczos coefficients): |x1 - x2| / |x| <= kappa (r1 + r2)
+    kappa, lo, hi = lanczos_kappa(sc["cg_coef"])
+    err_e = relerr(xev[0], xev[1])
+    bound = kappa * (res[0] + res[1])
     err = relerr(host(xm), host(xc))
-    say(f"  |x_mspcg - x_cg| / |x| = {err:.2e}")
+    say(f"  kappa(A) ~ {kappa:.4g} (spectrum [{lo:.3g}, {hi:.3g}]); even-site "
+        f"|x_mspcg - x_cg| / |x| = {err_e:.2e} <= {bound:.2e}; full x {err:.2e}")
+    assert err_e <= bound
     assert err <= 1e-7
 
 
@@ -129,3 +141,12 @@ def test_c5b_mspcg_32c64(c5b, block):
     r = (torch.linalg.vector_norm(dx - bd) / torch.linalg.vector_norm(bd)).item()
     say(f"  |D x - b| / |b| = {r:.2e}")
     assert r <= 1e-8
+    # the same residual measured by the oracle's D on 2000 sampled sites
+    del dx
+    rng = np.random.default_rng(7)
+    sites = np.sort(rng.choice(act.V4, size=2000, replace=False))
+    dxs = O.dwf_sites(act, U, host(x), sites)
+    bs = b.reshape(act.Ls, act.V4, 4, 3)[:, sites]
+    rs = relerr(dxs, bs)
+    say(f"  oracle |D x - b| / |b| on 2000 sampled sites = {rs:.2e}")
+    assert rs <= 1e-8
