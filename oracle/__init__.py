@@ -403,11 +403,21 @@ def block_precond_op(act: Action, U, p, block, mode: str = "literal", pad: int =
     mode "domain": A_s = P_s Mhat_Omega^+ Mhat_Omega P_s with Omega the block
       widened by `pad` sites in the cut directions (domain_schur).  pad = 0 is
       the Dirichlet block, pad = 2 reproduces the literal block (A reaches two
-      sites), and pad = 1 keeps only the paths that leave the block by one site."""
+      sites), and pad = 1 keeps only the paths that leave the block by one site.
+    mode "split": A_s = (P_s Mhat P_s)^+ (P_s Mhat P_s), the normal operator of
+      the diagonal block of Mhat (the block of the Schur operator is taken
+      before forming the normal equations, so paths whose middle even site
+      lies outside the block are dropped)."""
     ids = block_ids(act, block)
     if mode == "dirichlet":
         return normal(act, U, p, block)
     out = np.zeros_like(p)
+    if mode == "split":
+        for k in range(int(ids.max()) + 1):
+            m = (ids == k)[None, ..., None, None]
+            y = m * schur(act, U, m * p)
+            out += m * schur(act, U, y, dagger=True)
+        return out
     if mode == "domain":
         for k in range(int(ids.max()) + 1):
             m = (ids == k)[None, ..., None, None]

@@ -185,3 +185,27 @@ def test_domain_mask_wraps_periodically():
     assert list(np.flatnonzero(om1[:, 0, 0, 4])) == [0, 1, 2, 3, 4, 7]
     with pytest.raises(ValueError):
         O.domain_mask(O.Action((4, 4, 4, 8), 2, 1.8, 0.1), (2, 4, 4, 4), 0, 2)
+
+
+def test_split_block_is_normal_of_schur_block():
+    """The alternative block of Sec. 2.3's preconditioner where the block is
+    taken of Mhat before the normal equations: A_s = Mhat_ss^+ Mhat_ss with
+    Mhat_ss the diagonal block of the dense Schur complement of D."""
+    dims, Ls, blk = (4, 4, 2, 2), 2, (2, 2, 2, 2)
+    act, U, even, blk_of = _setup(dims, Ls, blk)
+    D = dense(lambda v: O.dwf(act, U, v), act.fshape)
+    ev = even.ravel()
+    Mh = D[np.ix_(ev, ev)] - D[np.ix_(ev, ~ev)] @ np.linalg.solve(D[np.ix_(~ev, ~ev)],
+                                                                   D[np.ix_(~ev, ev)])
+    Ks = dense(lambda v: O.block_precond_op(act, U, v, blk, "split"), act.fshape, even)
+    A = dense(lambda v: O.normal(act, U, v), act.fshape, even)
+    b = blk_of[even]
+    for k in range(int(b.max()) + 1):
+        sel = b == k
+        Mss = Mh[np.ix_(sel, sel)]
+        assert np.allclose(Ks[np.ix_(sel, sel)], Mss.conj().T @ Mss, rtol=0, atol=1e-13)
+        assert np.all(Ks[np.ix_(sel, ~sel)] == 0)
+    # it differs from the literal block P_s A P_s and is HPD
+    same = b[:, None] == b[None, :]
+    assert np.abs(Ks[same] - A[same]).max() > 1e-3
+    assert np.linalg.eigvalsh(Ks).min() > 0
