@@ -83,29 +83,186 @@ def hop_bytes_per_site(Ls: int, prec_bytes=192, link_bytes=144) -> float:
     return 2 * prec_bytes + 8 * link_bytes / Ls
 
 
-def cpu_baseline(w, U, b, seconds_target=12.0):
-    """The oracle's hop, timed on the host cores on a bounded sample of output
-    sites of the same lattice; reported in the metric's unit (GB/s)."""
-    import oracle as O
+def _cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    act = O.Action(w["dims"], w["Ls"], w["M5"], w["mf"], w["b"], w["c"])
-    V4 = int(np.prod(w["dims"]))
-    rng = np.random.default_rng(0)
+
+def _hop_sample(O, act, U, b, seconds, rng):
+    """Oracle hop on random output sites until `seconds` of CPU work: GB/s."""
+    V4 = int(np.prod(act.dims))
     O.hop_sites(act, U, b, rng.choice(V4, size=64, replace=False))  # thread pool warm-up
-    n_total, t_total, chunk = 0, 0.0, 2048
-    while t_total < seconds_target:
+    n_total, t_total, chunk = 0, 0.0, 1024
+    while t_total < seconds:
         sites = np.sort(rng.choice(V4, size=min(chunk, V4), replace=False))
         t0 = time.perf_counter()
         O.hop_sites(act, U, b, sites)
         t_total += time.perf_counter() - t0
         n_total += len(sites)
         chunk = min(2 * chunk, V4)
-    nbytes = n_total * w["Ls"] * hop_bytes_per_site(w["Ls"])
-    return {"value": round(nbytes / t_total / 1e9, 3), "unit": "GB/s", "cores": O.get_threads(),
-            "kind": "oracle",
-            "sample": f"oracle Wilson hop on {n_total} random output sites x Ls={w['Ls']} of the "
-                      f"{'x'.join(map(str, w['dims']))} lattice in {t_total:.1f} s; algorithmic "
-                      f"bytes {hop_bytes_per_site(w['Ls']):.0f} B per (x,s)"}
+    return n_total * act.Ls * hop_bytes_per_site(act.Ls) / t_total / 1e9, n_total, t_total
+
+
+def a_bytes_per_site(Ls: int) -> float:
+    """Algorithmic bytes of A = Mhat^+ Mhat per even (x, s) in FP64: four hops
+    and the two re-reads of the source for the M5op terms."""
+    return 4 * hop_bytes_per_site(Ls) + 2 * 192
+
+
+def cpu_baseline(w, U, b, gpu_iters=None, c2_iters=None, full=False):
+    """The oracle, as it stands, timed on the host cores on bounded samples of
+    the workload (reported beside the GPU figures, never a target):
+      value: the oracle's hop on random output sites, all threads, GB/s;
+      hop_1thread: the same with one thread;
+      A: one application of A = Mhat^+ Mhat on the whole lattice, GB/s;
+      cg: time to a 1e-10 true residual on the 4^4x8 Shamir workload
+          (measured), and on the 16^4x12 and the bench workload
+          extrapolated from a few timed oracle CG iterations times the
+          iteration count (the GPU's for the bench workload), labelled;
+          `full` times the 16^4x12 solve to the end instead (about a minute)."""
+    import oracle as O
+    from paper_1804_08593_amd import synth
+
+    rng = np.random.default_rng(0)
+    act = O.Action(w["dims"], w["Ls"], w["M5"], w["mf"], w["b"], w["c"])
+    nthreads = O.get_threads()
+    gbs, n_total, t_total = _hop_sample(O, act, U, b, 10.0, rng)
+    O.set_threads(1)
+    gbs1, n1, t1 = _hop_sample(O, act, U, b, 3.0, rng)
+    O.set_threads(nthreads)
+    out = {"value": round(gbs, 3), "unit": "GB/s", "cores": nthreads, "kind": "oracle",
+           "sample": f"oracle Wilson hop on {n_total} random output sites x Ls={w['Ls']} of the "
+                     f"{'x'.join(map(str, w['dims']))} lattice in {t_total:.1f} s with "
+                     f"{nthreads} threads; algorithmic bytes {hop_bytes_per_site(w['Ls']):.0f} B "
+                     f"per (x,s)",
+           "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+           "hop_1thread": {"GBps": round(gbs1, 3), "sites": n1, "seconds": round(t1, 1)}}
+    # A on the whole lattice
+    be = O.parity_mask(act, b, 0)
+    O.normal(act, U, be)  # workspace allocation
+    t0 = time.perf_counter()
+    O.normal(act, U, be)
+    ta = time.perf_counter() - t0
+    nh = act.V4 // 2 * act.Ls
+    out["A"] = {"GBps": round(nh * a_bytes_per_site(act.Ls) / ta / 1e9, 3),
+                "seconds": round(ta, 3),
+                "bytes_per_even_site": a_bytes_per_site(act.Ls)}
+    cg = {}
+    # 4^4 x 8 Shamir, mf = 0.1, links exp(0.3 i H): full solve
+    a1 = O.Action((4, 4, 4, 4), 8, 1.8, 0.1, 1.0, 0.0)
+    U1 = synth.gauge_field(a1.dims, 0.3, 1001)
+    b1 = synth.fermion_field(a1.dims, 8, 2001)
+    t0 = time.perf_counter()
+    _, i1 = O.solve(a1, U1, b1, tol=1e-10)
+    cg["dwf_shamir_4c4_ls8"] = {"seconds": round(time.perf_counter() - t0, 3),
+                                "iters": i1.iters, "measured": True}
+
+    def per_iter(a, Ua, ba, k=4):
+        _, bh = O.prepare(a, Ua, ba)
+        O.cg(a, Ua, bh, tol=1e-30, maxiter=1)
+        t0 = time.perf_counter()
+        O.cg(a, Ua, bh, tol=1e-30, maxiter=k)
+        return (time.perf_counter() - t0) / k, bh
+
+    a2 = O.Action((16, 16, 16, 16), 12, 1.8, 0.01, 1.5, 0.5)
+    U2 = synth.gauge_field(a2.dims, 0.2, 1002)
+    b2 = synth.fermion_field(a2.dims, 12, 2002)
+    if full:
+        t0 = time.perf_counter()
+        _, i2 = O.solve(a2, U2, b2, tol=1e-10)
+        cg["dwf_moebius_16c16_ls12"] = {"seconds": round(time.perf_counter() - t0, 2),
+                                        "iters": i2.iters, "measured": True}
+    elif c2_iters:
+        t_it, _ = per_iter(a2, U2, b2)
+        cg["dwf_moebius_16c16_ls12"] = {"seconds_per_iter": round(t_it, 4),
+                                        "extrapolated": f"per-iteration time x {c2_iters} "
+                                                        f"iterations (the GPU CG's count at "
+                                                        f"1e-10)",
+                                        "seconds": round(c2_iters * t_it, 1), "measured": False}
+    if gpu_iters:
+        t_it, _ = per_iter(act, U, b, k=2)
+        cg[w["name"]] = {"seconds_per_iter": round(t_it, 3), "measured": False,
+                         "extrapolated": f"per-iteration time x {gpu_iters} iterations (the "
+                                         f"GPU CG's count at 1e-10)",
+                         "seconds": round(gpu_iters * t_it, 1)}
+    out["cg_time_to_1e-10"] = cg
+    return out
+
+
+def c5b_dslash(args, log):
+    """FP64 dslash on the 32^3x64, Ls=12 lattice (fields 2.4 GB per parity,
+    far above the 256 MB Infinity Cache): HIP-event timing of the hop
+    launches of a fixed number of CG iterations."""
+    import torch
+
+    from paper_1804_08593_amd import mspcg, synth
+
+    w = WORKLOADS["dwf_moebius_32c64_ls12"]
+    log("[bench] generating dwf_moebius_32c64_ls12 for the dslash leg")
+    U = synth.gauge_field(w["dims"], w["eps"], w["gseed"])
+    b = synth.fermion_field(w["dims"], w["Ls"], w["rseed"])
+    ctx = mspcg.Context(w["dims"], w["Ls"], w["M5"], w["mf"], w["b"], w["c"])
+    ctx.load_gauge(torch.from_numpy(U).cuda())
+    del U
+    bd = torch.from_numpy(b).cuda()
+    del b
+    x = torch.zeros_like(bd)
+    tuning = None if args.no_autotune else ctx.autotune()
+    p = mspcg.make_params(tol=1e-30, maxiter=40, solver=mspcg.SOLVER_CG, timing=True)
+    ctx.solve(bd, x, p, allow_noconv=True)
+    st = ctx.solve(bd, x, p, allow_noconv=True)
+    res = {"workload": "dwf_moebius_32c64_ls12", "dims": list(w["dims"]), "Ls": w["Ls"],
+           "cg_iterations_timed": st["outer_iters"], "tuning": tuning}
+    for k in ("hop64", "hopcg"):
+        n = st["kernel_launches"][k]
+        if n:
+            gbs = st["kernel_bytes"][k] / (st["kernel_ms"][k] * 1e-3) / 1e9
+            res[k] = {"launches": n, "avg_us": round(1e3 * st["kernel_ms"][k] / n, 2),
+                      "bytes_per_launch": round(st["kernel_bytes"][k] / n),
+                      "GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    del bd, x, ctx
+    torch.cuda.empty_cache()
+    return res
+
+
+READINGS = [  # (name, pad, form): the block operator A_s of the preconditioner
+    ("dirichlet", 0, 0),   # Mhat_s^+ Mhat_s, hops between blocks dropped
+    ("pad1", 1, 0),        # P_s Mhat_W^+ Mhat_W P_s, W = block widened by one site
+    ("split", 1, 1),       # (P_s Mhat P_s)^+ (P_s Mhat P_s)
+    ("literal", 2, 0),     # P_s A P_s, the diagonal block of A (Sec. 2.3, Fig. 3)
+]
+
+
+def sweep_readings(ctx, w, bd, x, args, log):
+    """Outer iterations (the paper's global iterations, Sec. 3) and time of
+    MSPCG for each block reading and l, beside plain CG, on one GPU."""
+    from paper_1804_08593_amd import mspcg
+
+    p_cg = mspcg.make_params(tol=args.tol, maxiter=20000, solver=mspcg.SOLVER_CG)
+    ctx.solve(bd, x, p_cg)
+    cg = ctx.solve(bd, x, p_cg)
+    print(json.dumps({"workload": args.workload, "solver": "cg", "outer_iters": cg["outer_iters"],
+                      "seconds": round(cg["seconds"], 4)}), flush=True)
+    for name, pad, form in READINGS:
+        for l in (2, 3, 4, 6, 8):
+            p = mspcg.make_params(tol=args.tol, maxiter=20000, solver=mspcg.SOLVER_MSPCG,
+                                  block=w["block"], pad=pad, form=form, inner_iters=l,
+                                  inner_prec=mspcg.FP16)
+            ctx.solve(bd, x, p)  # domain set-up, untimed
+            st = ctx.solve(bd, x, p)
+            row = {"workload": args.workload, "solver": "mspcg", "reading": name,
+                   "block": list(w["block"]), "l": l, "outer_iters": st["outer_iters"],
+                   "g": round(cg["outer_iters"] / st["outer_iters"], 3),
+                   "seconds": round(st["seconds"], 4),
+                   "speedup_vs_cg": round(cg["seconds"] / st["seconds"], 3),
+                   "true_rel_resid": st["true_rel_resid"]}
+            print(json.dumps(row), flush=True)
+            log(f"[sweep] {name} l={l}: {st['outer_iters']} it {st['seconds']:.3f} s")
 
 
 def main():
@@ -118,6 +275,14 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--inner-iters", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="time the oracle's 16^4x12 CG solve to the end (about a minute)")
+    ap.add_argument("--no-c5b", action="store_true", help="skip the 32^3x64 dslash leg")
+    ap.add_argument("--no-fp64-inner", action="store_true")
+    ap.add_argument("--sweep-readings", action="store_true",
+                    help="instead of the bench line: MSPCG with the workload's blocks for "
+                         "every block reading (Dirichlet, pad 1, split Schur, literal) and "
+                         "l = 2..8, one JSON line per solve")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-tuned-blocking", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-10)
@@ -162,6 +327,10 @@ def main():
         tuning = ctx.autotune(block=w["block"], pad=2)
         tuning["seconds"] = round(time.perf_counter() - t0, 2)
         log(f"[bench] autotune: {tuning}")
+
+    if args.sweep_readings:
+        sweep_readings(ctx, w, bd, x, args, log)
+        return
 
     p_cg = mspcg.make_params(tol=args.tol, maxiter=20000, solver=mspcg.SOLVER_CG, timing=True)
     p_ms = mspcg.make_params(tol=args.tol, maxiter=20000, solver=mspcg.SOLVER_MSPCG,
@@ -284,9 +453,35 @@ def main():
                                         "inner_iters_total": last["mspcg_tuned"]["inner_iters_total"],
                                         "true_rel_resid": last["mspcg_tuned"]["true_rel_resid"],
                                         "speedup_vs_cg": round(cg_s / mt_s, 3)}
+    if run_ms and not args.no_fp64_inner:
+        # the same MSPCG with FP64 local solves (untimed): its outer count is
+        # the one the oracle's FP64 MSPCG reaches (within one iteration on the
+        # lattices the oracle can solve)
+        p64 = mspcg.make_params(tol=args.tol, maxiter=20000, solver=mspcg.SOLVER_MSPCG,
+                                block=w["block"], pad=2, inner_iters=args.inner_iters,
+                                inner_prec=mspcg.FP64)
+        s64 = ctx.solve(bd, x, p64)
+        line["mspcg_fp64_inner"] = {"outer_iters": s64["outer_iters"],
+                                    "seconds": round(s64["seconds"], 4),
+                                    "true_rel_resid": s64["true_rel_resid"]}
+        log(f"[bench] FP64-inner MSPCG: {s64['outer_iters']} outer iterations")
+    if not args.no_c5b:
+        line["c5b_dslash"] = c5b_dslash(args, log)
+        log(f"[bench] 32^3x64 dslash: {line['c5b_dslash'].get('hop64')}")
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(w, U, b)
+        w = dict(w, name=args.workload)
+        # the GPU CG's iteration count on 16^4x12 (scales the oracle's
+        # per-iteration time there)
+        w2 = WORKLOADS["dwf_moebius_16c16_ls12"]
+        c2 = mspcg.Context(w2["dims"], w2["Ls"], w2["M5"], w2["mf"], w2["b"], w2["c"])
+        c2.load_gauge(torch.from_numpy(synth.gauge_field(w2["dims"], w2["eps"],
+                                                         w2["gseed"])).cuda())
+        b2 = torch.from_numpy(synth.fermion_field(w2["dims"], w2["Ls"], w2["rseed"])).cuda()
+        s2 = c2.solve(b2, torch.zeros_like(b2), mspcg.make_params(tol=args.tol, maxiter=20000))
+        del c2, b2
+        line["cpu_baseline"] = cpu_baseline(w, U, b, gpu_iters=last["cg"]["outer_iters"],
+                                            c2_iters=s2["outer_iters"], full=args.cpu_full)
     print(json.dumps(line), flush=True)
 
 

@@ -104,26 +104,33 @@ enum {
 enum {
     MSPCG_SOLVER_CG = 0,       /* plain FP64 CG on A */
     MSPCG_SOLVER_MIXED_CG = 1, /* FP32 CG iterations, FP64 solution and reliable updates */
-    MSPCG_SOLVER_MSPCG = 2     /* FP64 flexible outer PCG, sloppy block preconditioner */
+    MSPCG_SOLVER_MSPCG = 2,    /* FP64 flexible outer PCG, sloppy block preconditioner */
+    MSPCG_SOLVER_MULTISPLIT = 3 /* the multisplitting iteration of Sec. 2.1, eq. (2), alone:
+                                  x += K_l^-1 (bhat - A x), FP64 residual every sweep; it
+                                  converges slowly or not at all (Sec. 2.2) */
 };
 
 /* Block decomposition of the preconditioner (Sec. 2.3, eq. (5), Fig. 3).
- * block[mu] divides dims[mu] and is even.  Each block's operator is
- * A_s = P_s Mhat_W^+ Mhat_W P_s, where W is the block widened by `pad` sites
- * on both sides of every direction that holds more than one block, and
- * Mhat_W is the even-odd Schur complement of the principal submatrix of D on
- * W (every hop into or out of W dropped):
+ * block[mu] divides dims[mu] and is even.  With form = MSPCG_FORM_DOMAIN each
+ * block's operator is A_s = P_s Mhat_W^+ Mhat_W P_s, where W is the block
+ * widened by `pad` sites on both sides of every direction that holds more
+ * than one block, and Mhat_W is the even-odd Schur complement of the
+ * principal submatrix of D on W (every hop into or out of W dropped):
  *   pad = 2: exactly the paper's A_s = P_s A P_s (the diagonal block of A,
  *            including every path that leaves the block and comes back);
  *   pad = 0: the Dirichlet-cut block Mhat_s^+ Mhat_s (no hop between blocks);
  *   pad = 1: only the paths that leave the block by one site come back.
+ * With form = MSPCG_FORM_SPLIT (pad 1 or 2) the block is taken of Mhat before
+ * the normal equations: A_s = (P_s Mhat P_s)^+ (P_s Mhat P_s).
  * In a cut direction dims[mu] - block[mu] >= 2 pad is required (the widened
  * block must not wrap onto itself).  With FP16 local solves one widened
  * block must hold fewer than 2^24 sites per parity and under 4 GB per FP16
  * field (MSPCG_EUNSUPPORTED otherwise). */
+enum { MSPCG_FORM_DOMAIN = 0, MSPCG_FORM_SPLIT = 1 };
 typedef struct {
     int block[4];
     int pad;
+    int form;
 } mspcg_blocking;
 
 typedef struct {
@@ -131,10 +138,10 @@ typedef struct {
     int maxiter;          /* outer iterations */
     int solver;           /* MSPCG_SOLVER_* */
     int use_x0;           /* 1: x holds the initial guess on entry (even part used) */
-    mspcg_blocking blocking; /* MSPCG only; block[0] == 0: the context's blocking
-                                (mspcg_set_blocking) is used */
-    int inner_iters;      /* l: local CG iterations per outer iteration (MSPCG) */
-    int inner_prec;       /* MSPCG_FP16 / FP32 / FP64 for the local solves (MSPCG) */
+    mspcg_blocking blocking; /* MSPCG and MULTISPLIT; block[0] == 0: the context's
+                                blocking (mspcg_set_blocking) is used */
+    int inner_iters;      /* l: local CG iterations per outer iteration (MSPCG, MULTISPLIT) */
+    int inner_prec;       /* MSPCG_FP16 / FP32 / FP64 for the local solves (MSPCG, MULTISPLIT) */
     int check_every;      /* host convergence poll interval in iterations (0: auto) */
     double delta;         /* reliable-update threshold of the mixed CG (0: 0.1) */
     int timing;           /* 1: record per-kernel-class times with HIP events */

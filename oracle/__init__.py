@@ -296,6 +296,9 @@ class SolveInfo:
     true_rel_resid: float = float("nan")
     history: list = field(default_factory=list)
     converged: bool = False
+    # (alpha_k, beta_k) of every iteration: the Lanczos tridiagonal they
+    # define has the Ritz values of the (preconditioned) operator
+    coef: list = field(default_factory=list)
 
 
 def cg(act: Action, U, bhat, tol=1e-10, maxiter=10000, x0=None, block=None):
@@ -330,6 +333,7 @@ def cg(act: Action, U, bhat, tol=1e-10, maxiter=10000, x0=None, block=None):
                 return x, info
             r = rt
             rr_new = norm2(r)
+        info.coef.append((alpha, rr_new / rr))
         p = r + (rr_new / rr) * p
         rr = rr_new
     info.true_rel_resid = np.sqrt(norm2(bhat - A(x))) / bnorm
@@ -528,6 +532,7 @@ def mspcg(act: Action, U, bhat, block, l: int, tol=1e-10, maxiter=10000, x0=None
         z_new = K(r_new)
         # a replaced residual restarts the recurrence (p = z)
         beta = 0.0 if restart else dot(z_new, r_new - r).real / zr
+        info.coef.append((alpha, beta))
         zr = dot(z_new, r_new).real
         p = z_new + beta * p
         r = r_new

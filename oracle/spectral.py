@@ -1,0 +1,167 @@
+"""Spectral study of the multisplitting preconditioner (Sec. 4.2).
+
+TEST INFRASTRUCTURE / ANALYSIS ONLY: built on the oracle, never imported by
+the product.  Sec. 4.2 argues that the high modes of A are local, so the
+block-diagonal K = (+)_s A_s (eq. (5)) captures them and lowers the condition
+number of the preconditioned operator; only the low, global modes are left
+to the outer CG, which is why a sloppy local solve (a few local iterations,
+low precision) is enough.  This module measures that on small lattices:
+
+  * exact K: the spectrum of K^-1 A (dense generalized eigenproblem) for
+    several block sizes and the three block readings (the paper's literal
+    P_s A P_s, the Dirichlet-cut block, the split-Schur block);
+  * the locality claim itself: for every eigenvector v of A the ratio
+    v^+ K v / v^+ A v (1 when K acts on v as A does);
+  * sloppy K_l: Ritz values of K_l^-1 A from the outer PCG's coefficients
+    (Lanczos tridiagonal), and the outer iteration count, against l.
+
+Run `python -m oracle.spectral` to print the tables (a few minutes).
+"""
+from __future__ import annotations
+
+import sys
+import time
+
+import numpy as np
+import scipy.linalg
+
+from . import (Action, block_precond_op, mspcg, normal, parity_mask, prepare)
+
+
+def even_mask(act: Action) -> np.ndarray:
+    """Boolean fermion-shaped mask of the even sites."""
+    ones = np.ones(act.fshape, dtype=np.complex128)
+    return parity_mask(act, ones, 0) != 0
+
+
+def dense_even(act: Action, f) -> np.ndarray:
+    """Dense matrix of a linear map on even fields, restricted to even sites."""
+    ev = even_mask(act)
+    idx = np.flatnonzero(ev.ravel())
+    n = len(idx)
+    M = np.empty((n, n), dtype=np.complex128)
+    e = np.zeros(act.fshape, dtype=np.complex128)
+    flat = e.reshape(-1)
+    for j, i in enumerate(idx):
+        flat[i] = 1.0
+        M[:, j] = f(e).reshape(-1)[idx]
+        flat[i] = 0.0
+    return M
+
+
+def dense_A(act: Action, U) -> np.ndarray:
+    return dense_even(act, lambda v: normal(act, U, v))
+
+
+def dense_K(act: Action, U, A, block, mode: str) -> np.ndarray:
+    """Dense K = (+)_s A_s.  The literal block is A with its off-block entries
+    zeroed (eq. (5), Fig. 3); the other readings come from the oracle's
+    block operator."""
+    if mode == "literal":
+        from . import block_ids
+        ids = np.broadcast_to(block_ids(act, block)[None, ..., None, None], act.fshape)
+        b = ids[even_mask(act)]
+        K = np.where(b[:, None] == b[None, :], A, 0)
+        return K
+    return dense_even(act, lambda v: block_precond_op(act, U, v, block, mode))
+
+
+def precond_eigs(A: np.ndarray, K: np.ndarray) -> np.ndarray:
+    """Eigenvalues of K^-1 A (ascending): the generalized Hermitian problem
+    A v = lambda K v, K Hermitian positive definite."""
+    return scipy.linalg.eigh(A, K, eigvals_only=True)
+
+
+def rayleigh_ratios(A: np.ndarray, K: np.ndarray):
+    """Eigenvalues lambda_i of A and q_i = v_i^+ K v_i / lambda_i for its
+    eigenvectors v_i (1 where K acts on v_i as A does)."""
+    lam, V = np.linalg.eigh(A)
+    q = np.real(np.einsum("ji,jk,ki->i", V.conj(), K, V)) / lam
+    return lam, q
+
+
+def ritz_from_coef(coef) -> np.ndarray:
+    """Ritz values of the Lanczos tridiagonal of CG / PCG coefficients
+    (alpha_j, beta_j): T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},
+    T_j,j+1 = sqrt(beta_j)/alpha_j."""
+    c = np.asarray(coef, dtype=float)
+    a, b = c[:, 0], c[:, 1]
+    n = len(a)
+    d = 1.0 / a
+    d[1:] += b[:-1] / a[:-1]
+    e = np.sqrt(np.maximum(b[:-1], 0.0)) / a[:-1]
+    return scipy.linalg.eigh_tridiagonal(d, e, eigvals_only=True)
+
+
+def _fmt(x):
+    return f"{x:.3g}"
+
+
+def study(out=sys.stdout):
+    t0 = time.time()
+    w = out.write
+    # --- exact preconditioner on 4^4 x Ls=4 (dense, 6144 even-site unknowns)
+    dims, Ls = (4, 4, 4, 4), 4
+    act = Action(dims, Ls, 1.8, 0.01, 1.5, 0.5)
+    from paper_1804_08593_amd import synth
+    U = synth.gauge_field(dims, 0.25, 4001)
+    A = dense_A(act, U)
+    lamA = np.linalg.eigvalsh(A)
+    w(f"## Exact block preconditioner, {dims} x Ls={Ls}, Moebius b=1.5 c=0.5 M5=1.8 mf=0.01, "
+      f"links exp(0.25 i H) seed 4001\n\n")
+    w(f"A = Mhat^+ Mhat: spectrum [{_fmt(lamA[0])}, {_fmt(lamA[-1])}], kappa(A) = "
+      f"{_fmt(lamA[-1] / lamA[0])}\n\n")
+    w("| blocks | block | reading | lmin(K^-1 A) | lmax(K^-1 A) | kappa(K^-1 A) | kappa(A) / kappa |\n")
+    w("|---|---|---|---|---|---|---|\n")
+    blockings = [(2, 2, 2, 2), (4, 2, 2, 2), (4, 4, 2, 2), (4, 4, 4, 2)]
+    Ks = {}
+    for blk in blockings:
+        nb = int(np.prod([dims[m] // blk[m] for m in range(4)]))
+        for mode in ("literal", "split", "dirichlet"):
+            K = dense_K(act, U, A, blk, mode)
+            ev = precond_eigs(A, K)
+            Ks[(blk, mode)] = K
+            kap = ev[-1] / ev[0]
+            w(f"| {nb} | {'x'.join(map(str, blk))} | {mode} | {_fmt(ev[0])} | {_fmt(ev[-1])} | "
+              f"{_fmt(kap)} | {_fmt(lamA[-1] / lamA[0] / kap)} |\n")
+            out.flush()
+    # --- locality: v^+ K v / v^+ A v across the spectrum of A (literal K, 16 blocks)
+    w("\n## How K acts on the eigenvectors of A (literal K)\n\n")
+    w("q = v^+ K v / v^+ A v for the eigenvectors v of A, averaged over deciles of the "
+      "spectrum (decile 1 = lowest modes).\n\n")
+    w("| blocks | " + " | ".join(f"d{i}" for i in range(1, 11)) + " |\n")
+    w("|---|" + "---|" * 10 + "\n")
+    for blk in blockings:
+        nb = int(np.prod([dims[m] // blk[m] for m in range(4)]))
+        lam, q = rayleigh_ratios(A, Ks[(blk, "literal")])
+        dec = np.array_split(q, 10)
+        w(f"| {nb} | " + " | ".join(_fmt(np.mean(d)) for d in dec) + " |\n")
+        out.flush()
+    # --- sloppy local solves: outer iterations and Ritz values against l
+    dims2, Ls2 = (4, 4, 4, 4), 8
+    act2 = Action(dims2, Ls2, 1.8, 0.01, 1.5, 0.5)
+    U2 = synth.gauge_field(dims2, 0.25, 4002)
+    b2 = synth.fermion_field(dims2, Ls2, 4003)
+    _, bhat = prepare(act2, U2, b2)
+    w(f"\n## Sloppy local solves K_l (l local CG iterations), {dims2} x Ls={Ls2}, "
+      f"literal blocks, outer flexible PCG to 1e-10\n\n")
+    w("Ritz values of K_l^-1 A from the outer PCG's Lanczos coefficients "
+      "(l = 0: plain CG, i.e. of A itself).\n\n")
+    w("| blocks | l | outer iterations | Ritz min | Ritz max | kappa_eff |\n|---|---|---|---|---|---|\n")
+    from . import cg
+    _, info0 = cg(act2, U2, bhat, tol=1e-10)
+    r0 = ritz_from_coef(info0.coef)
+    w(f"| - | 0 | {info0.iters} | {_fmt(r0[0])} | {_fmt(r0[-1])} | {_fmt(r0[-1] / r0[0])} |\n")
+    for blk in ((2, 2, 2, 2), (4, 4, 2, 2)):
+        nb = int(np.prod([dims2[m] // blk[m] for m in range(4)]))
+        for l in (1, 2, 3, 4, 6, 8, 12):
+            _, info = mspcg(act2, U2, bhat, blk, l, tol=1e-10)
+            r = ritz_from_coef(info.coef)
+            w(f"| {nb} | {l} | {info.iters} | {_fmt(r[0])} | {_fmt(r[-1])} | "
+              f"{_fmt(r[-1] / r[0])} |\n")
+            out.flush()
+    w(f"\n(study time {time.time() - t0:.0f} s)\n")
+
+
+if __name__ == "__main__":
+    study()

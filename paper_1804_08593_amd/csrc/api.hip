@@ -636,6 +636,8 @@ extern "C" int mspcg_set_blocking(mspcg_ctx* c, const mspcg_blocking* b) {
         if (b->block[m] < 2 || (b->block[m] & 1) || c->L[m] % b->block[m]) return MSPCG_EINVAL;
     }
     if (b->pad < 0 || b->pad > 2) return MSPCG_EINVAL;
+    if (b->form != MSPCG_FORM_DOMAIN && b->form != MSPCG_FORM_SPLIT) return MSPCG_EINVAL;
+    if (b->form == MSPCG_FORM_SPLIT && b->pad < 1) return MSPCG_EINVAL;
     c->blocking = *b;
     c->has_blocking = true;
     return MSPCG_OK;

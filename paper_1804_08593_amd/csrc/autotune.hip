@@ -60,9 +60,10 @@ int time_ms(hipStream_t st, int reps, F f, float& ms) {
 
 std::string cache_key(const mspcg_ctx* c, const mspcg_blocking* bk) {
     char k[256];
-    snprintf(k, sizeof(k), "dims=%dx%dx%dx%d Ls=%d block=%dx%dx%dx%d pad=%d", c->L[0], c->L[1],
+    snprintf(k, sizeof(k), "dims=%dx%dx%dx%d Ls=%d block=%dx%dx%dx%d pad=%d%s", c->L[0], c->L[1],
              c->L[2], c->L[3], c->Ls, bk ? bk->block[0] : 0, bk ? bk->block[1] : 0,
-             bk ? bk->block[2] : 0, bk ? bk->block[3] : 0, bk ? bk->pad : 0);
+             bk ? bk->block[2] : 0, bk ? bk->block[3] : 0, bk ? bk->pad : 0,
+             bk && bk->form == MSPCG_FORM_SPLIT ? " split" : "");
     return k;
 }
 
@@ -199,13 +200,14 @@ __global__ void fill_hash_kernel(double* p, long n, unsigned long long seed) {
     p[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
-std::vector<mspcg_blocking> block_candidates(const mspcg_ctx* c, int pad) {
+std::vector<mspcg_blocking> block_candidates(const mspcg_ctx* c, int pad, int form) {
     std::vector<mspcg_blocking> v;
     auto ok = [&](int L, int b) { return b >= 2 && !(b & 1) && L % b == 0 && (L == b || L - b >= 2 * pad); };
     // every non-empty set of halved directions, then a quarter in every direction
     for (int mask = 1; mask < 16; ++mask) {
         mspcg_blocking b;
         b.pad = pad;
+        b.form = form;
         bool good = true;
         for (int m = 0; m < 4; ++m) {
             b.block[m] = (mask >> m) & 1 ? c->L[m] / 2 : c->L[m];
@@ -215,6 +217,7 @@ std::vector<mspcg_blocking> block_candidates(const mspcg_ctx* c, int pad) {
     }
     mspcg_blocking q;
     q.pad = pad;
+    q.form = form;
     bool good = true;
     for (int m = 0; m < 4; ++m) {
         q.block[m] = c->L[m] >= 16 ? c->L[m] / 4 : c->L[m] / 2;
@@ -232,7 +235,8 @@ extern "C" int mspcg_tune_blocking(mspcg_ctx* c, const mspcg_solve_params* base,
     if (!c->gauge) return MSPCG_ENOGAUGE;
     MSPCG_HIP(hipSetDevice(c->device));
     const int pad = base->blocking.pad > 0 || base->blocking.block[0] ? base->blocking.pad : 2;
-    std::vector<mspcg_blocking> cands = block_candidates(c, pad);
+    const int form = base->blocking.block[0] ? base->blocking.form : MSPCG_FORM_DOMAIN;
+    std::vector<mspcg_blocking> cands = block_candidates(c, pad, form);
     if (cands.empty()) return MSPCG_EUNSUPPORTED;
     const size_t n = (size_t)c->V4 * c->Ls * 12;
     double2* b = (double2*)c->buf("tb.b", n * sizeof(double2));

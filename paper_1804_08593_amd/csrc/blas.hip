@@ -253,6 +253,16 @@ __global__ void zero_kernel(double2* y, long n) {
         y[i] = make_double2(0.0, 0.0);
 }
 
+// x += z, skipped once the solve's `done` flag is set
+__global__ void xpy_kernel(double2* x, const double2* z, long n, const int* done) {
+    if (done && *done) return;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        const double2 a = x[i], b = z[i];
+        x[i] = make_double2(a.x + b.x, a.y + b.y);
+    }
+}
+
 __global__ void scale_kernel(double2* y, const double2* x, double a, long n) {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long)gridDim.x * blockDim.x) {
@@ -264,6 +274,12 @@ __global__ void scale_kernel(double2* y, const double2* x, double a, long n) {
 int last_error() { return hipGetLastError() == hipSuccess ? 0 : -2; }
 
 }  // namespace
+
+int launch_xpy(double2* x, const double2* z, long N, const int* done, hipStream_t st) {
+    hipLaunchKernelGGL(xpy_kernel, dim3((unsigned)blas_grid_x(12 * N)), dim3(kThreads), 0, st, x,
+                       z, 12 * N, done);
+    return last_error();
+}
 
 int launch_scale(double2* y, const double2* x, double a, long n, hipStream_t st) {
     hipLaunchKernelGGL(scale_kernel, dim3((unsigned)blas_grid_x(n)), dim3(kThreads), 0, st, y, x,

@@ -43,6 +43,7 @@ struct Domains {
     int nb[4];
     int ndom;
     int pad;
+    int form;      // MSPCG_FORM_DOMAIN / MSPCG_FORM_SPLIT
     Box interior;  // block, offset 0
     Box pad1;      // block padded by min(pad,1)
     Box pad2;      // block padded by min(pad,2) (also the link box)
@@ -60,6 +61,15 @@ struct Domains {
     long n_y, rd_y;
     int* list_v;
     long n_v, rd_v;
+    // box of the middle even field y = Mhat_D p: the widened block (within
+    // distance 2 through list_y) for FORM_DOMAIN, the block itself for
+    // FORM_SPLIT
+    const Box& ybox() const { return form == MSPCG_FORM_SPLIT ? interior : pad2; }
+    const int* ylist() const { return form == MSPCG_FORM_SPLIT ? nullptr : list_y; }
+    long yn() const { return form == MSPCG_FORM_SPLIT ? 0 : n_y; }
+    long yread() const { return form == MSPCG_FORM_SPLIT ? 0 : rd_y; }
+    // output sites of the y hop (its partials count)
+    long yout() const { return ylist() ? n_y : ybox().Vh; }
 };
 
 }  // namespace mspcg

@@ -254,32 +254,46 @@ constexpr int hop_min_waves() {
     return (S::has_scale && !EPA && !CG && (LS == 8 || LS == 16)) ? 6 : MSPCG_HOP_MINWAVES;
 }
 
-template <class S, int LS, bool DAG, bool EPH, bool EPA, bool CG = false>
-__global__ __launch_bounds__(256, (hop_min_waves<S, LS, EPA, CG>())) void hop_kernel(HopArgs<S> a) {
+// LDS layout of one hop workgroup (SPB sites x LS lanes).
+template <class S, int LS>
+struct HopShape {
     using T = typename S::real;
     using E = typename S::elem;
-    constexpr int SPB = 256 / LS;
+    static constexpr int SPB = 256 / LS;
     // s-exchange array, component-major with a padded row per (site, component):
     // entry (site, s, c) at (site * 12 + c) * LSP + s, so the lanes of a site
     // (consecutive s) and the chain threads (consecutive c) both hit distinct banks
-    constexpr int LSP = LS + 1;
+    static constexpr int LSP = LS + 1;
     // FP16 links are decoded to FP32 once, when staged; LE is the LDS entry
     using LE = typename std::conditional<S::has_scale, nt_f2, E>::type;
-    constexpr int NCH = 72 * (int)sizeof(E) / 16;   // 16-byte chunks of one site's links
-    constexpr int LSTR = 72 * (int)sizeof(LE) / 16 + 1;  // padded LDS site stride (chunks)
-    constexpr bool LDSL = SPB * LSTR * 16 <= 40 * 1024;
+    static constexpr int NCH = 72 * (int)sizeof(E) / 16;   // 16-byte chunks of one site's links
+    static constexpr int LSTR = 72 * (int)sizeof(LE) / 16 + 1;  // padded LDS site stride (chunks)
+    static constexpr bool LDSL = SPB * LSTR * 16 <= 40 * 1024;
     // the s-exchange array serves both the chain programs (EPH/EPA) and the
     // single-step programs applied by neighbour exchange
-    constexpr int EPI_BYTES = SPB * 12 * LSP * (int)sizeof(cx<T>);
-    constexpr int LNK_BYTES = LDSL ? SPB * LSTR * 16 : 16;
-    constexpr int LDS_BYTES = EPI_BYTES > LNK_BYTES ? EPI_BYTES : LNK_BYTES;
-    __shared__ __attribute__((aligned(16))) unsigned char smem[LDS_BYTES];
+    static constexpr int EPI_BYTES = SPB * 12 * LSP * (int)sizeof(cx<T>);
+    static constexpr int LNK_BYTES = LDSL ? SPB * LSTR * 16 : 16;
+    static constexpr int LDS_BYTES = EPI_BYTES > LNK_BYTES ? EPI_BYTES : LNK_BYTES;
+};
+
+// One workgroup's share of a hop launch: output sites [bx*SPB, (bx+1)*SPB)
+// of domain d (in traversal order); gx = workgroups per domain (indexes the
+// partial sums); smem: HopShape<S, LS>::LDS_BYTES of LDS, 16-byte aligned.
+template <class S, int LS, bool DAG, bool EPH, bool EPA, bool CG>
+__device__ __forceinline__ void hop_body(const HopArgs<S>& a, int bx, int d, int gx,
+                                         unsigned char* smem) {
+    using T = typename S::real;
+    using E = typename S::elem;
+    using SH = HopShape<S, LS>;
+    constexpr int SPB = SH::SPB;
+    constexpr int LSP = SH::LSP;
+    using LE = typename SH::LE;
+    constexpr int NCH = SH::NCH;
+    constexpr int LSTR = SH::LSTR;
+    constexpr bool LDSL = SH::LDSL;
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
     nt_u4* lnk = reinterpret_cast<nt_u4*>(smem);
 
-    if (a.done && *a.done) return;
-    int bx, d;
-    logical_block(a.xcd_remap, bx, d);
     const int sl = threadIdx.x / LS;
     const int s = threadIdx.x - sl * LS;
     const long t_lin = (long)bx * SPB + sl;  // position in the traversal order
@@ -566,7 +580,7 @@ __global__ __launch_bounds__(256, (hop_min_waves<S, LS, EPA, CG>())) void hop_ke
                 store_spinor_at<S>(a.cg_x, obase, s, LS, v);
             }
         }
-        block_sum_store<S, LS>(n2, a.partials + (long)d * gridDim.x + bx);
+        block_sum_store<S, LS>(n2, a.partials + (long)d * gx + bx);
         return;
     }
     if (active) store_spinor_at<S, MSPCG_HOP_NT>(a.out, obase, s, LS, res);
@@ -583,8 +597,17 @@ __global__ __launch_bounds__(256, (hop_min_waves<S, LS, EPA, CG>())) void hop_ke
             }
             n2 = (double)t2;
         }
-        block_sum_store<S, LS>(n2, a.partials + (long)d * gridDim.x + bx);
+        block_sum_store<S, LS>(n2, a.partials + (long)d * gx + bx);
     }
+}
+
+template <class S, int LS, bool DAG, bool EPH, bool EPA, bool CG = false>
+__global__ __launch_bounds__(256, (hop_min_waves<S, LS, EPA, CG>())) void hop_kernel(HopArgs<S> a) {
+    __shared__ __attribute__((aligned(16))) unsigned char smem[HopShape<S, LS>::LDS_BYTES];
+    if (a.done && *a.done) return;
+    int bx, d;
+    logical_block(a.xcd_remap, bx, d);
+    hop_body<S, LS, DAG, EPH, EPA, CG>(a, bx, d, (int)gridDim.x, smem);
 }
 
 template <class S, int LS>

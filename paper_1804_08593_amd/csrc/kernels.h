@@ -160,6 +160,8 @@ int launch_copy_norm(double2* dst, const double2* src, long N, double* partials,
 int launch_dot2(const double2* z, const double2* r, const double2* q, long N, double* partials,
                 long nparts, hipStream_t st);
 int launch_zero(double2* y, long N, hipStream_t st);
+// x += z on N whole-lattice entries (skipped when *done)
+int launch_xpy(double2* x, const double2* z, long N, const int* done, hipStream_t st);
 // y = a x on n complex values (any layout)
 int launch_scale(double2* y, const double2* x, double a, long n, hipStream_t st);
 

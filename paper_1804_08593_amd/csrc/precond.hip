@@ -226,12 +226,14 @@ static size_t link_elems(const Domains& D) {
 
 int domains_setup(mspcg_ctx* c, const mspcg_blocking& bk, int prec, hipStream_t st) {
     Domains& D = c->dom;
-    bool same = D.built && D.prec == prec && D.pad == bk.pad;
+    bool same = D.built && D.prec == prec && D.pad == bk.pad && D.form == bk.form;
     for (int m = 0; m < 4; ++m) same = same && D.blk[m] == bk.block[m];
     if (same) return 0;
     D.built = false;  // until every field below describes the new blocking
     if (prec != MSPCG_FP16 && prec != MSPCG_FP32 && prec != MSPCG_FP64) return MSPCG_EINVAL;
     if (bk.pad < 0 || bk.pad > 2) return MSPCG_EINVAL;
+    if (bk.form != MSPCG_FORM_DOMAIN && bk.form != MSPCG_FORM_SPLIT) return MSPCG_EINVAL;
+    if (bk.form == MSPCG_FORM_SPLIT && bk.pad < 1) return MSPCG_EINVAL;
     int ndom = 1;
     for (int m = 0; m < 4; ++m) {
         const int b = bk.block[m];
@@ -245,6 +247,7 @@ int domains_setup(mspcg_ctx* c, const mspcg_blocking& bk, int prec, hipStream_t 
     if (ndom > kMaxDomains) return MSPCG_EUNSUPPORTED;
     D.ndom = ndom;
     D.pad = bk.pad;
+    D.form = bk.form;
     D.interior = dom_box(c, D, 0);
     D.pad1 = dom_box(c, D, bk.pad < 1 ? bk.pad : 1);
     D.pad2 = dom_box(c, D, bk.pad < 2 ? bk.pad : 2);
@@ -424,18 +427,19 @@ int block_A(mspcg_ctx* c, Field<S> w, CField<S> p, double* partials, const int* 
     if ((e = dom_hop<S>(c, u, D.pad1, cfield(t), D.interior, 1, false, P.X, nullptr, D.interior,
                         P.id, nullptr, done, st)))
         return e;
-    // y = M5op p - D_h^eo u / 4  (even, pad 2, within distance 2) = Mhat_D p
-    if ((e = dom_hop<S>(c, y, D.pad2, cfield(u), D.pad1, 0, false, m14, &p, D.interior, P.M5,
-                        partials, done, st, nullptr, D.list_y, D.n_y, D.rd_y)))
+    // y = M5op p - D_h^eo u / 4 = Mhat_D p  (even: widened block within
+    // distance 2, or the block itself for the split form)
+    if ((e = dom_hop<S>(c, y, D.ybox(), cfield(u), D.pad1, 0, false, m14, &p, D.interior, P.M5,
+                        partials, done, st, nullptr, D.ylist(), D.yn(), D.yread())))
         return e;
     // v = X^+ Dd^oe y  (odd, pad 1, within distance 1)
-    if ((e = dom_hop<S>(c, v, D.pad1, cfield(y), D.pad2, 1, true, P.Xdag, nullptr, D.interior,
+    if ((e = dom_hop<S>(c, v, D.pad1, cfield(y), D.ybox(), 1, true, P.Xdag, nullptr, D.interior,
                         P.id, nullptr, done, st, nullptr, D.list_v, D.n_v, D.rd_v)))
         return e;
     // w = M5op^+ y - B^+ Dd^eo v / 4  (even, block)
     CField<S> yc = cfield(y);
     return dom_hop<S>(c, w, D.interior, cfield(v), D.pad1, 0, true, scaled(P.Bdag, -0.25, -0.25),
-                      &yc, D.pad2, P.M5dag, nullptr, done, st);
+                      &yc, D.ybox(), P.M5dag, nullptr, done, st);
 }
 
 // One local CG step on every block with the vector updates fused into the
@@ -477,13 +481,13 @@ static int block_cg_step(mspcg_ctx* c, Field<S> p, Field<S> rho, Field<S> z,
     if ((e = dom_hop<S>(c, u, D.pad1, cfield(t), D.interior, 1, false, P.X, nullptr, D.interior,
                         P.id, nullptr, done, st)))
         return e;
-    if ((e = dom_hop<S>(c, y, D.pad2, cfield(u), D.pad1, 0, false, m14, &pc, D.interior, P.M5,
-                        part, done, st, nullptr, D.list_y, D.n_y, D.rd_y)))
+    if ((e = dom_hop<S>(c, y, D.ybox(), cfield(u), D.pad1, 0, false, m14, &pc, D.interior, P.M5,
+                        part, done, st, nullptr, D.ylist(), D.yn(), D.yread())))
         return e;
     hipLaunchKernelGGL(inner_alpha, dim3(D.ndom), dim3(kThreads), 0, st, sc, part, (int)hop_np,
                        done);
     if (last_error()) return MSPCG_EHIP;
-    if ((e = dom_hop<S>(c, v, D.pad1, cfield(y), D.pad2, 1, true, P.Xdag, nullptr, D.interior,
+    if ((e = dom_hop<S>(c, v, D.pad1, cfield(y), D.ybox(), 1, true, P.Xdag, nullptr, D.interior,
                         P.id, nullptr, done, st, nullptr, D.list_v, D.n_v, D.rd_v)))
         return e;
     HopArgs<S> cg;
@@ -497,7 +501,7 @@ static int block_cg_step(mspcg_ctx* c, Field<S> p, Field<S> rho, Field<S> z,
     Field<S> none;
     memset(&none, 0, sizeof(none));
     return dom_hop<S>(c, none, D.interior, cfield(v), D.pad1, 0, true, scaled(P.Bdag, -0.25, -0.25),
-                      &yc, D.pad2, P.M5dag, part, done, st, &cg);
+                      &yc, D.ybox(), P.M5dag, part, done, st, &cg);
 }
 
 static InnerScalars inner_scalars(mspcg_ctx* c) {
@@ -524,7 +528,7 @@ static int precond_core(mspcg_ctx* c, int l, CField<F64> r, Field<F64> z, const 
     Field<S> zz = half_field<S>(c, pf + "z", D.ndom * nd);
     if (!rho.data || !p.data || !zz.data) return MSPCG_ENOMEM;
     InnerScalars sc = inner_scalars(c);
-    const long hop_np = hop_grid_x<S>(D.list_y ? D.n_y : D.pad2.Vh, Ls);
+    const long hop_np = hop_grid_x<S>(D.yout(), Ls);
     const int spb = kThreads / Ls;
     const long start_np = (D.interior.Vh + spb - 1) / spb;
     const long vec_np = (nd + kThreads - 1) / kThreads;
@@ -579,7 +583,7 @@ size_t precond_partials_need(mspcg_ctx* c) {
     const Domains& D = c->dom;
     const int Ls = c->Ls;
     const long nd = D.interior.Vh * Ls;
-    const long hop_np = hop_grid_x<F64>(D.list_y ? D.n_y : D.pad2.Vh, Ls);
+    const long hop_np = hop_grid_x<F64>(D.yout(), Ls);
     const int spb = kThreads / Ls;
     const long start_np = (D.interior.Vh + spb - 1) / spb;
     const long vec_np = (nd + kThreads - 1) / kThreads;

@@ -403,7 +403,82 @@ struct MixedSolver : Solver {
     }
 };
 
+// The multisplitting iteration (Sec. 2.1, eq. (2)) as a solver of its own:
+// every block solves its local system with the other blocks' current
+// solution as Dirichlet data, which for the block-diagonal K is the sweep
+//   x += K_l^-1 (bhat - A x),
+// the local solves run on the correction from a zero guess (eq. (4) on the
+// first sweep).  The residual is recomputed in FP64 after every sweep, so
+// the iterated residual is the true one.
+template <class S>
+struct MultisplitSolver : Solver {
+    Field<F64> r, z, q;
+    long npb = 0;
+    int cap = 0, l = 0;
+    int check_default() const override { return 4; }
+    int init(hipStream_t st) override {
+        r = half_field<F64>(c, "d.cg_r", c->Nh);
+        z = half_field<F64>(c, "d.cg_z", c->Nh);
+        q = half_field<F64>(c, "d.cg_q", c->Nh);
+        if (!r.data || !z.data || !q.data) return MSPCG_ENOMEM;
+        int e;
+        if ((e = domains_setup(c, p->blocking, p->inner_prec, st))) return e;
+        npb = blas_grid_x(12 * c->Nh);
+        size_t need = 4 * (size_t)npb + 16;
+        const size_t pneed = precond_partials_need(c);
+        if (pneed > need) need = pneed;
+        if ((e = ensure_partials(c, need))) return e;
+        cap = p->maxiter + 1;
+        if ((e = ensure_hist(c, cap))) return e;
+        l = p->inner_iters;
+        double rr;
+        if (x0) {
+            if ((e = true_residual(c, r, bhat, cfield(x), st, rr))) return e;
+        } else {
+            MSPCG_HIP(hipMemsetAsync(x.data, 0, (size_t)12 * c->Nh * sizeof(double2), st));
+            if ((e = norm2_sync(c, bhat.data, r.data, st, rr))) return e;
+        }
+        memset(&s, 0, sizeof(s));
+        s.rr = rr;
+        s.bb = bb;
+        s.tol2 = p->tol * p->tol * bb;
+        s.done = rr <= s.tol2 ? 1 : 0;
+        true_rr = rr;
+        return push(c, st, s);
+    }
+    // z = K_l^-1 r ; x += z ; r = bhat - A x with |r|^2
+    int iterate(hipStream_t st) override {
+        int e;
+        const int* done = &c->sc->done;
+        if ((e = precond_apply_flag<S>(c, l, cfield(r), z, done, st))) return e;
+        if (launch_xpy(x.data, z.data, c->Nh, done, st)) return MSPCG_EHIP;
+        if ((e = op_A<F64>(c, q, cfield(x), nullptr, done, st))) return e;
+        if (launch_sub_norm(r.data, bhat.data, q.data, c->Nh, c->partials, npb, st))
+            return MSPCG_EHIP;
+        if (launch_cg_beta(c->sc, c->partials, (int)npb, c->hist, cap, st)) return MSPCG_EHIP;
+        return 0;
+    }
+    int after_poll(hipStream_t) override {
+        const int new_iters = s.iter - iters;
+        iters = s.iter;
+        inner_total += l * new_iters;
+        true_rr = s.rr;
+        if (s.breakdown) {
+            breakdown = finished = true;
+            return 0;
+        }
+        if (s.done) converged = finished = true;
+        if (iters >= p->maxiter) finished = true;
+        return 0;
+    }
+};
+
 std::unique_ptr<Solver> make_solver(const mspcg_solve_params* p) {
+    if (p->solver == MSPCG_SOLVER_MULTISPLIT) {
+        if (p->inner_prec == MSPCG_FP16) return std::unique_ptr<Solver>(new MultisplitSolver<F16>());
+        if (p->inner_prec == MSPCG_FP32) return std::unique_ptr<Solver>(new MultisplitSolver<F32>());
+        return std::unique_ptr<Solver>(new MultisplitSolver<F64>());
+    }
     if (p->solver == MSPCG_SOLVER_CG) return std::unique_ptr<Solver>(new CGSolver());
     if (p->solver == MSPCG_SOLVER_MIXED_CG) return std::unique_ptr<Solver>(new MixedSolver());
     if (p->inner_prec == MSPCG_FP16) return std::unique_ptr<Solver>(new MSPCGSolver<F16>());
@@ -415,18 +490,22 @@ std::unique_ptr<Solver> make_solver(const mspcg_solve_params* p) {
 // blocking (mspcg_set_blocking), so each system of a batch can have its own.
 mspcg_solve_params effective(const mspcg_ctx* c, const mspcg_solve_params* p) {
     mspcg_solve_params q = *p;
-    if (q.solver == MSPCG_SOLVER_MSPCG && q.blocking.block[0] == 0 && c->has_blocking)
+    if ((q.solver == MSPCG_SOLVER_MSPCG || q.solver == MSPCG_SOLVER_MULTISPLIT) &&
+        q.blocking.block[0] == 0 && c->has_blocking)
         q.blocking = c->blocking;
     return q;
 }
 
 int validate(const mspcg_ctx* c, const mspcg_solve_params* p) {
     if (p->maxiter < 0 || !(p->tol > 0)) return MSPCG_EINVAL;
-    if (p->solver < MSPCG_SOLVER_CG || p->solver > MSPCG_SOLVER_MSPCG) return MSPCG_EINVAL;
-    if (p->solver == MSPCG_SOLVER_MSPCG) {
+    if (p->solver < MSPCG_SOLVER_CG || p->solver > MSPCG_SOLVER_MULTISPLIT) return MSPCG_EINVAL;
+    if (p->solver == MSPCG_SOLVER_MSPCG || p->solver == MSPCG_SOLVER_MULTISPLIT) {
         if (p->inner_iters < 0) return MSPCG_EINVAL;
         if (p->inner_prec < MSPCG_FP64 || p->inner_prec > MSPCG_FP16) return MSPCG_EINVAL;
         if (p->blocking.pad < 0 || p->blocking.pad > 2) return MSPCG_EINVAL;
+        if (p->blocking.form != MSPCG_FORM_DOMAIN && p->blocking.form != MSPCG_FORM_SPLIT)
+            return MSPCG_EINVAL;
+        if (p->blocking.form == MSPCG_FORM_SPLIT && p->blocking.pad < 1) return MSPCG_EINVAL;
         for (int m = 0; m < 4; ++m) {
             const int b = p->blocking.block[m];
             if (b < 2 || (b & 1) || c->L[m] % b) return MSPCG_EINVAL;
@@ -592,7 +671,8 @@ int solve_batch(mspcg_ctx* const* cs, int n, const void* const* b, void* const* 
         ps[i] = effective(cs[i], p);
         if ((e = validate(cs[i], &ps[i]))) return e;
     }
-    if (p->solver == MSPCG_SOLVER_MIXED_CG) return MSPCG_EUNSUPPORTED;
+    if (p->solver == MSPCG_SOLVER_MIXED_CG || p->solver == MSPCG_SOLVER_MULTISPLIT)
+        return MSPCG_EUNSUPPORTED;
     if (n == 0) return MSPCG_OK;
     MSPCG_HIP(hipSetDevice(cs[0]->device));
     hipStream_t st;

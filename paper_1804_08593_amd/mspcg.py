@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_PKG, "libmspcg.so")
 OK, EINVAL, ENOMEM, EHIP, ENOGAUGE, ENOCONV, EBREAKDOWN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 OP_D, OP_DDAG, OP_HOP, OP_HOPDAG, OP_MHAT, OP_MHATDAG, OP_A, OP_M5INV, OP_PREPARE, OP_KBLOCK = range(10)
 FP64, FP32, FP16 = 0, 1, 2
-SOLVER_CG, SOLVER_MIXED_CG, SOLVER_MSPCG = 0, 1, 2
+SOLVER_CG, SOLVER_MIXED_CG, SOLVER_MSPCG, SOLVER_MULTISPLIT = 0, 1, 2, 3
+FORM_DOMAIN, FORM_SPLIT = 0, 1
 KC_HOP64, KC_HOP32, KC_HOPDOM, KC_FIVED, KC_BLAS, KC_HOPCG, KC_HOPDOMCG = range(7)
 KC_NAMES = ("hop64", "hop32", "hopdom", "fived", "blas", "hopcg", "hopdomcg")
 KC_COUNT = 7
@@ -43,7 +44,7 @@ class Action(ctypes.Structure):
 
 
 class Blocking(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_int * 4), ("pad", ctypes.c_int)]
+    _fields_ = [("block", ctypes.c_int * 4), ("pad", ctypes.c_int), ("form", ctypes.c_int)]
 
 
 class Tuning(ctypes.Structure):
@@ -147,12 +148,13 @@ def _ptr(t):
 
 def make_params(tol=1e-10, maxiter=10000, solver=SOLVER_CG, use_x0=False, block=(0, 0, 0, 0),
                 pad=2, inner_iters=6, inner_prec=FP16, check_every=0, delta=0.1,
-                timing=False, rhs_normal=False) -> SolveParams:
+                timing=False, rhs_normal=False, form=FORM_DOMAIN) -> SolveParams:
     p = SolveParams()
     p.tol, p.maxiter, p.solver, p.use_x0 = float(tol), int(maxiter), int(solver), int(use_x0)
     for i in range(4):
         p.blocking.block[i] = int(block[i])
     p.blocking.pad = int(pad)
+    p.blocking.form = int(form)
     p.inner_iters, p.inner_prec = int(inner_iters), int(inner_prec)
     p.check_every, p.delta, p.timing = int(check_every), float(delta), int(timing)
     p.rhs_normal = int(bool(rhs_normal))
@@ -221,11 +223,12 @@ class Context:
                                   _stream(stream)), "mspcg_apply")
         return out
 
-    def set_blocking(self, block, pad=2):
+    def set_blocking(self, block, pad=2, form=FORM_DOMAIN):
         b = Blocking()
         for i in range(4):
             b.block[i] = int(block[i])
         b.pad = int(pad)
+        b.form = int(form)
         _check(load().mspcg_set_blocking(self._h, ctypes.byref(b)), "mspcg_set_blocking")
 
     def precond(self, r, z, inner_iters, prec=FP16, stream=None):

@@ -142,3 +142,49 @@ def test_mspcg_pad1_solve_matches_oracle():
     _, info = O.solve(act, U, b, tol=1e-10, precond=(blk, 4, "domain", 1))
     say(f"pad1 MSPCG: gpu {st['outer_iters']} oracle {info.iters}")
     assert abs(st["outer_iters"] - info.iters) <= 1
+
+
+@functools.lru_cache(maxsize=None)
+def _split_ref(geom):
+    dims, Ls, blk = GEOMS[geom]
+    act = O.Action(dims, Ls, 1.8, 0.05, 1.5, 0.5)
+    U = synth.gauge_field(dims, 0.25, 31)
+    psi = O.parity_mask(act, synth.fermion_field(dims, Ls, 32), 0)
+    return psi, O.block_precond_op(act, U, psi, blk, "split")
+
+
+@pytest.mark.parametrize("prec", [mspcg.FP64, mspcg.FP32, mspcg.FP16])
+@pytest.mark.parametrize("pad", [1, 2])
+@pytest.mark.parametrize("geom", sorted(GEOMS))
+def test_split_block_operator_geometry(geom, pad, prec):
+    """A_s = (P_s Mhat P_s)^+ (P_s Mhat P_s) (MSPCG_FORM_SPLIT) on every geometry."""
+    dims, Ls, blk, act, U, ctx = _ctx(geom)
+    ctx.set_blocking(blk, pad, mspcg.FORM_SPLIT)
+    psi, ref = _split_ref(geom)
+    out = torch.zeros(ctx.fshape, dtype=torch.complex128, device="cuda")
+    ctx.apply(mspcg.OP_KBLOCK, dev(psi), out, prec=prec)
+    got = host(out)
+    err, serr = relerr(got, ref), site_err(got, ref)
+    say(f"split K geom={geom} pad={pad} prec={prec}: relerr {err:.3e} max entry err {serr:.3e}")
+    tol, stol = KTOL[prec]
+    assert err <= tol and serr <= stol
+
+
+def test_split_form_mspcg_and_validation():
+    dims, Ls, blk, act, U, ctx = _ctx("cut4", seed=41)
+    b = synth.fermion_field(dims, Ls, 42)
+    x = torch.zeros(ctx.fshape, dtype=torch.complex128, device="cuda")
+    prm = mspcg.make_params(tol=1e-10, maxiter=500, solver=mspcg.SOLVER_MSPCG, block=blk, pad=1,
+                            inner_iters=4, inner_prec=mspcg.FP16, form=mspcg.FORM_SPLIT)
+    st = ctx.solve(dev(b), x, prm)
+    say(f"split-form MSPCG: {st['outer_iters']} iterations")
+    assert st["converged"] and st["true_rel_resid"] <= 1e-10
+    x_ref, _ = O.solve(act, U, b, tol=1e-13)
+    assert relerr(host(x), x_ref) <= 1e-8
+    with pytest.raises(mspcg.MspcgError) as e:  # the split form needs the pad-1 odd sites
+        ctx.set_blocking(blk, 0, mspcg.FORM_SPLIT)
+    assert e.value.code == mspcg.EINVAL
+    with pytest.raises(mspcg.MspcgError) as e:
+        ctx.solve(dev(b), x, mspcg.make_params(solver=mspcg.SOLVER_MSPCG, block=blk, pad=2,
+                                               form=7))
+    assert e.value.code == mspcg.EINVAL
