@@ -62,7 +62,8 @@ enum {
     MSPCG_ENOGAUGE = -4,  /* operator used before mspcg_load_gauge */
     MSPCG_ENOCONV = -5,   /* solve stopped at maxiter; x holds the last iterate */
     MSPCG_EBREAKDOWN = -6,/* non-positive curvature or non-finite value in a solve */
-    MSPCG_EUNSUPPORTED = -7 /* Ls not compiled in, or an unsupported combination */
+    MSPCG_EUNSUPPORTED = -7, /* Ls not compiled in, or an unsupported combination */
+    MSPCG_ESCRATCH = -8   /* lattice too large for the fixed scratch of mspcg_apply_noalloc */
 };
 
 typedef struct mspcg_ctx mspcg_ctx;
@@ -230,6 +231,26 @@ int mspcg_gauge_generation(mspcg_ctx* ctx, unsigned long long* gen);
  * MSPCG_OP_KBLOCK uses the blocking set by mspcg_set_blocking. */
 int mspcg_apply(mspcg_ctx* ctx, int op, int prec, const void* in_dev, void* out_dev,
                 hipStream_t stream);
+
+/* Allocation-free variant of mspcg_apply, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, and
+ * harnesses that forbid hipMalloc.  Same operators (MSPCG_OP_D ...
+ * MSPCG_OP_PREPARE; MSPCG_OP_KBLOCK gives MSPCG_EUNSUPPORTED), precisions
+ * (FP64, FP32), layouts, asynchrony and results as mspcg_apply; the
+ * context's gauge field must already be loaded.  Its intermediate fields
+ * live in one fixed scratch array per GPU of MSPCG_NOALLOC_SCRATCH_BYTES,
+ * held by the library from load to process end, instead of context
+ * buffers; no hipMalloc, hipFree or other allocating call is made.  An
+ * application needs 8 one-parity fields, 8 * (V4/2) * Ls * 12 * 16 bytes in
+ * FP64 (half in FP32), each rounded up to 256 bytes; a larger lattice is
+ * rejected with MSPCG_ESCRATCH before any work is queued (FP64 reaches
+ * V4 * Ls = 174762, e.g. 8^3x16 at Ls = 16).  Every call on one GPU shares
+ * that GPU's scratch and leaves its contents behind: calls on one stream
+ * are ordered, but calls that overlap in time on one GPU (several streams
+ * or host threads without ordering) race and give undefined results. */
+#define MSPCG_NOALLOC_SCRATCH_BYTES (128u << 20)
+int mspcg_apply_noalloc(mspcg_ctx* ctx, int op, int prec, const void* in_dev, void* out_dev,
+                        hipStream_t stream);
 
 /* Blocking used by MSPCG_OP_KBLOCK and mspcg_precond. */
 int mspcg_set_blocking(mspcg_ctx* ctx, const mspcg_blocking* blocking);

@@ -335,6 +335,15 @@ MSPCG_OPS(F32)
 }  // namespace mspcg
 
 void* mspcg_ctx::buf(const std::string& name, size_t bytes) {
+    if (arena) {
+        auto a = arena_slots.find(name);
+        if (a != arena_slots.end()) return a->second.second >= bytes ? arena + a->second.first : nullptr;
+        const size_t off = (arena_used + 255) & ~(size_t)255;
+        if (off + bytes > arena_cap) return nullptr;
+        arena_slots[name] = {off, bytes};
+        arena_used = off + bytes;
+        return arena + off;
+    }
     auto it = bufs.find(name);
     if (it != bufs.end() && it->second.second >= bytes) return it->second.first;
     if (it != bufs.end()) {
@@ -373,6 +382,7 @@ extern "C" const char* mspcg_strerror(int code) {
         case MSPCG_ENOCONV: return "solver did not converge within maxiter";
         case MSPCG_EBREAKDOWN: return "solver breakdown (non-positive curvature or non-finite value)";
         case MSPCG_EUNSUPPORTED: return "unsupported Ls or option";
+        case MSPCG_ESCRATCH: return "lattice too large for the fixed scratch of the allocation-free entry point";
         default: return "unknown error";
     }
 }
@@ -396,6 +406,7 @@ extern "C" int mspcg_create(const mspcg_action* a, int device, mspcg_ctx** out) 
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return MSPCG_EHIP;
     if (hipSetDevice(device) != hipSuccess) return MSPCG_EHIP;
+    if (int e = noalloc_init(device)) return e;
     mspcg_ctx* c = new (std::nothrow) mspcg_ctx();
     if (!c) return MSPCG_ENOMEM;
     c->act = *a;
@@ -427,6 +438,8 @@ extern "C" int mspcg_create(const mspcg_action* a, int device, mspcg_ctx** out) 
     c->partials = nullptr;
     c->partials_len = 0;
     c->has_blocking = false;
+    c->arena = nullptr;
+    c->arena_cap = c->arena_used = 0;
     memset(&c->dom, 0, sizeof(c->dom));
     c->timing = false;
     c->evused = 0;
@@ -608,9 +621,14 @@ extern "C" int mspcg_apply(mspcg_ctx* c, int op, int prec, const void* in_dev, v
             return MSPCG_EHIP;
         return MSPCG_OK;
     }
+    return apply_op(c, op, prec, (const double2*)in_dev, (double2*)out_dev, st);
+}
+
+int mspcg::apply_op(mspcg_ctx* c, int op, int prec, const double2* in, double2* out,
+                    hipStream_t st) {
     if (op < 0 || op > MSPCG_OP_PREPARE) return MSPCG_EINVAL;
-    if (prec == MSPCG_FP64) return apply_prec<F64>(c, op, (const double2*)in_dev, (double2*)out_dev, st);
-    if (prec == MSPCG_FP32) return apply_prec<F32>(c, op, (const double2*)in_dev, (double2*)out_dev, st);
+    if (prec == MSPCG_FP64) return apply_prec<F64>(c, op, in, out, st);
+    if (prec == MSPCG_FP32) return apply_prec<F32>(c, op, in, out, st);
     return MSPCG_EINVAL;
 }
 

@@ -93,6 +93,11 @@ struct mspcg_ctx {
     int warnings;                  // MSPCG_WARN_* bits found by mspcg_create
     // buffers
     std::map<std::string, std::pair<void*, size_t>> bufs;
+    // allocation-free mode (mspcg_apply_noalloc): while `arena` is set, buf()
+    // carves named fields out of it instead of allocating
+    char* arena;
+    size_t arena_cap, arena_used;
+    std::map<std::string, std::pair<size_t, size_t>> arena_slots;
     double* partials;
     size_t partials_len;
     mspcg::DevScalars* sc;
@@ -195,6 +200,11 @@ int kblock_apply(mspcg_ctx* c, CField<F64> p_e, Field<F64> q_e, hipStream_t st);
 template <class S>
 int block_A(mspcg_ctx* c, Field<S> w, CField<S> p, double* partials, const int* done,
             hipStream_t st);
+
+// mspcg_apply's operators (every op but MSPCG_OP_KBLOCK) in FP64 or FP32
+int apply_op(mspcg_ctx* c, int op, int prec, const double2* in, double2* out, hipStream_t st);
+// the allocation-free scratch of the current device (set up by mspcg_create)
+int noalloc_init(int device);
 
 int solve_one(mspcg_ctx* c, const void* b_dev, void* x_dev, const mspcg_solve_params* p,
               mspcg_solve_stats* stats, hipStream_t st);

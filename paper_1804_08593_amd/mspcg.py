@@ -16,6 +16,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmspcg.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOGAUGE, ENOCONV, EBREAKDOWN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+ESCRATCH = -8
+NOALLOC_SCRATCH_BYTES = 128 << 20
 OP_D, OP_DDAG, OP_HOP, OP_HOPDAG, OP_MHAT, OP_MHATDAG, OP_A, OP_M5INV, OP_PREPARE, OP_KBLOCK = range(10)
 FP64, FP32, FP16 = 0, 1, 2
 SOLVER_CG, SOLVER_MIXED_CG, SOLVER_MSPCG, SOLVER_MULTISPLIT = 0, 1, 2, 3
@@ -27,7 +29,8 @@ EXPORTS = ("mspcg_create", "mspcg_destroy", "mspcg_strerror", "mspcg_version",
            "mspcg_load_gauge", "mspcg_apply", "mspcg_set_blocking", "mspcg_precond",
            "mspcg_solve", "mspcg_solve_batch", "mspcg_force", "mspcg_get_tuning",
            "mspcg_set_tuning", "mspcg_autotune", "mspcg_tune_blocking",
-           "mspcg_get_warnings", "mspcg_gauge_generation", "mspcg_pseudofermion_action")
+           "mspcg_get_warnings", "mspcg_gauge_generation", "mspcg_pseudofermion_action",
+           "mspcg_apply_noalloc")
 WARN_M5_RANGE = 1
 
 
@@ -100,6 +103,7 @@ def load(path: str = LIB_PATH):
         lib.mspcg_version.restype = I
         lib.mspcg_load_gauge.argtypes = [P, P, P]
         lib.mspcg_apply.argtypes = [P, I, I, P, P, P]
+        lib.mspcg_apply_noalloc.argtypes = [P, I, I, P, P, P]
         lib.mspcg_set_blocking.argtypes = [P, ctypes.POINTER(Blocking)]
         lib.mspcg_precond.argtypes = [P, I, I, P, P, P]
         lib.mspcg_solve.argtypes = [P, P, P, ctypes.POINTER(SolveParams),
@@ -221,6 +225,12 @@ class Context:
     def apply(self, op, inp, out, prec=FP64, stream=None):
         _check(load().mspcg_apply(self._h, int(op), int(prec), _ptr(inp), _ptr(out),
                                   _stream(stream)), "mspcg_apply")
+        return out
+
+    def apply_noalloc(self, op, inp, out, prec=FP64, stream=None):
+        """mspcg_apply without device allocation (fixed per-GPU scratch)."""
+        _check(load().mspcg_apply_noalloc(self._h, int(op), int(prec), _ptr(inp), _ptr(out),
+                                          _stream(stream)), "mspcg_apply_noalloc")
         return out
 
     def set_blocking(self, block, pad=2, form=FORM_DOMAIN):
