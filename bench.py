@@ -230,6 +230,55 @@ def c5b_dslash(args, log):
     return res
 
 
+# six uneven lattices solved together: dims, Ls, mf (b=1.5, c=0.5, M5=1.8,
+# links exp(0.25 i H)); gauge seed 1040 + i, source seed 2040 + i
+BATCH = [((8, 8, 8, 8), 8, 0.05), ((12, 12, 12, 12), 12, 0.01), ((16, 16, 16, 16), 16, 0.05),
+         ((12, 12, 12, 24), 8, 0.01), ((16, 16, 16, 32), 12, 0.05), ((20, 20, 20, 20), 16, 0.01)]
+
+
+def batch_compare(args):
+    """Batched MSPCG of the six lattices (blockings from the library's
+    blocking autotuner) with the local solves' block hops as persistent
+    multi-lattice launches (batch_kernels 0) and as one launch per lattice
+    and stage (batch_kernels 1); median of 3 after one warm-up."""
+    import torch
+
+    from paper_1804_08593_amd import mspcg, synth
+
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    ctxs, bs = [], []
+    base = mspcg.make_params(tol=args.tol, maxiter=3000, solver=mspcg.SOLVER_MSPCG,
+                             inner_iters=args.inner_iters, inner_prec=mspcg.FP16)
+    for i, (d, Ls, mf) in enumerate(BATCH):
+        c = mspcg.Context(d, Ls, 1.8, mf, 1.5, 0.5)
+        c.load_gauge(torch.from_numpy(synth.gauge_field(d, 0.25, 1040 + i)).cuda())
+        blk = c.tune_blocking(base, probe_iters=6)
+        log(f"[batch] {d} Ls={Ls}: blocking {blk}")
+        ctxs.append(c)
+        bs.append(torch.from_numpy(synth.fermion_field(d, Ls, 2040 + i)).cuda())
+    for kern in (0, 1):
+        p = mspcg.make_params(tol=args.tol, maxiter=3000, solver=mspcg.SOLVER_MSPCG,
+                              inner_iters=args.inner_iters, inner_prec=mspcg.FP16,
+                              batch_kernels=kern)
+        times, sts = [], None
+        for rep in range(4):
+            xs = [torch.zeros_like(b) for b in bs]
+            sts = mspcg.solve_batch(ctxs, bs, xs, p)
+            if rep:
+                times.append(sts[0]["seconds"])
+        print(json.dumps({"batch_kernels": kern, "persistent": sts[0]["batch_persistent"],
+                          "seconds": round(float(np.median(times)), 4),
+                          "outer_iters": [st["outer_iters"] for st in sts],
+                          "true_rel_resid": [st["true_rel_resid"] for st in sts]}), flush=True)
+    # each lattice alone (eager solves), for the total of separate solves
+    tot = 0.0
+    for c, b in zip(ctxs, bs):
+        x = torch.zeros_like(b)
+        c.solve(b, x, base)
+        tot += c.solve(b, x, base)["seconds"]
+    print(json.dumps({"separate_solves_seconds": round(tot, 4)}), flush=True)
+
+
 READINGS = [  # (name, pad, form): the block operator A_s of the preconditioner
     ("dirichlet", 0, 0),   # Mhat_s^+ Mhat_s, hops between blocks dropped
     ("pad1", 1, 0),        # P_s Mhat_W^+ Mhat_W P_s, W = block widened by one site
@@ -279,6 +328,10 @@ def main():
                     help="time the oracle's 16^4x12 CG solve to the end (about a minute)")
     ap.add_argument("--no-c5b", action="store_true", help="skip the 32^3x64 dslash leg")
     ap.add_argument("--no-fp64-inner", action="store_true")
+    ap.add_argument("--batch", action="store_true",
+                    help="instead of the bench line: the six uneven lattices solved together "
+                         "with persistent multi-lattice block hops and with one launch per "
+                         "lattice, one JSON line per variant")
     ap.add_argument("--sweep-readings", action="store_true",
                     help="instead of the bench line: MSPCG with the workload's blocks for "
                          "every block reading (Dirichlet, pad 1, split Schur, literal) and "
@@ -307,6 +360,9 @@ def main():
 
     from paper_1804_08593_amd import mspcg, synth
 
+    if args.batch:
+        batch_compare(args)
+        return
     w = WORKLOADS[args.workload]
     dims, Ls = w["dims"], w["Ls"]
     log = lambda *a: print(*a, file=sys.stderr, flush=True)

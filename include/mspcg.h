@@ -148,6 +148,11 @@ typedef struct {
     int timing;           /* 1: record per-kernel-class times with HIP events */
     int rhs_normal;       /* 1: b is an even field solved directly as A x = b (x: even
                              field, odd sites zero); 0: solve D x = b */
+    int batch_kernels;    /* mspcg_solve_batch with MSPCG: 0 = each block-hop stage of the
+                             local solves runs for every lattice in one persistent launch over
+                             a (lattice, block, tile) work list that skips converged lattices
+                             (when every lattice's Ls is 8, 12 or 16 and there are at most 8);
+                             1 = one launch per lattice and stage */
 } mspcg_solve_params;
 
 /* Launch tuning.  Hop kernels visit their output sites in 4D tiles so that
@@ -191,6 +196,8 @@ typedef struct {
                               they define bounds the spectrum of A from inside */
     int cg_coef_cap;       /* iterations the buffer holds */
     int cg_coef_len;
+    int batch_persistent;  /* mspcg_solve_batch: 1 when the local solves' block hops ran as
+                              persistent multi-lattice launches */
 } mspcg_solve_stats;
 
 /* Warning bits reported by mspcg_get_warnings. */

@@ -25,7 +25,7 @@ import time
 import numpy as np
 import scipy.linalg
 
-from . import (Action, block_precond_op, mspcg, normal, parity_mask, prepare)
+from . import (Action, block_precond_op, mspcg, normal, parity_mask, prepare, schur)
 
 
 def even_mask(act: Action) -> np.ndarray:
@@ -53,15 +53,28 @@ def dense_A(act: Action, U) -> np.ndarray:
     return dense_even(act, lambda v: normal(act, U, v))
 
 
-def dense_K(act: Action, U, A, block, mode: str) -> np.ndarray:
+def _even_block_ids(act: Action, block) -> np.ndarray:
+    from . import block_ids
+    ids = np.broadcast_to(block_ids(act, block)[None, ..., None, None], act.fshape)
+    return ids[even_mask(act)]
+
+
+def dense_K(act: Action, U, A, block, mode: str, Mhat=None) -> np.ndarray:
     """Dense K = (+)_s A_s.  The literal block is A with its off-block entries
-    zeroed (eq. (5), Fig. 3); the other readings come from the oracle's
-    block operator."""
+    zeroed (eq. (5), Fig. 3); the split block is, per block, Mhat_ss^+ Mhat_ss
+    from the dense Schur operator Mhat (given, or built); the Dirichlet block
+    comes from the oracle's block operator."""
+    b = _even_block_ids(act, block)
     if mode == "literal":
-        from . import block_ids
-        ids = np.broadcast_to(block_ids(act, block)[None, ..., None, None], act.fshape)
-        b = ids[even_mask(act)]
-        K = np.where(b[:, None] == b[None, :], A, 0)
+        return np.where(b[:, None] == b[None, :], A, 0)
+    if mode == "split":
+        if Mhat is None:
+            Mhat = dense_even(act, lambda v: schur(act, U, v))
+        K = np.zeros_like(A)
+        for k in np.unique(b):
+            sel = np.flatnonzero(b == k)
+            Mss = Mhat[np.ix_(sel, sel)]
+            K[np.ix_(sel, sel)] = Mss.conj().T @ Mss
         return K
     return dense_even(act, lambda v: block_precond_op(act, U, v, block, mode))
 
@@ -106,6 +119,7 @@ def study(out=sys.stdout):
     from paper_1804_08593_amd import synth
     U = synth.gauge_field(dims, 0.25, 4001)
     A = dense_A(act, U)
+    Mhat = dense_even(act, lambda v: schur(act, U, v))
     lamA = np.linalg.eigvalsh(A)
     w(f"## Exact block preconditioner, {dims} x Ls={Ls}, Moebius b=1.5 c=0.5 M5=1.8 mf=0.01, "
       f"links exp(0.25 i H) seed 4001\n\n")
@@ -118,7 +132,7 @@ def study(out=sys.stdout):
     for blk in blockings:
         nb = int(np.prod([dims[m] // blk[m] for m in range(4)]))
         for mode in ("literal", "split", "dirichlet"):
-            K = dense_K(act, U, A, blk, mode)
+            K = dense_K(act, U, A, blk, mode, Mhat)
             ev = precond_eigs(A, K)
             Ks[(blk, mode)] = K
             kap = ev[-1] / ev[0]

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -196,6 +197,18 @@ int precond_apply_flag(mspcg_ctx* c, int l, CField<F64> r, Field<F64> z, const i
                        hipStream_t st, PrecondDots* dots = nullptr);
 template <class S>
 int kblock_apply(mspcg_ctx* c, CField<F64> p_e, Field<F64> q_e, hipStream_t st);
+// The local solves of several lattices (mspcg_solve_batch) interleaved stage
+// by stage; with `multi`, each block-hop stage of every lattice runs in one
+// persistent multi-lattice launch (when every lattice's Ls allows it).
+struct BatchPrecond {
+    bool multi = false;
+    virtual ~BatchPrecond() {}
+    // z[i] = K_l^-1 r[i] on every lattice; dots[i] as in precond_apply_flag
+    virtual int apply(int l, const CField<F64>* r, const Field<F64>* z, PrecondDots* dots,
+                      hipStream_t st) = 0;
+};
+int make_batch_precond(mspcg_ctx* const* cs, int n, int prec, int l, const int* const* done,
+                       bool multi, std::unique_ptr<BatchPrecond>& out);
 // w = A_s p on every block (domain layout, precision S)
 template <class S>
 int block_A(mspcg_ctx* c, Field<S> w, CField<S> p, double* partials, const int* done,

@@ -669,4 +669,52 @@ long hop_grid_x(long Vh, int Ls) {
     return (Vh + spb - 1) / spb;
 }
 
+template <class S>
+constexpr int multi_lds_bytes() {
+    constexpr int a = HopShape<S, 8>::LDS_BYTES, b = HopShape<S, 12>::LDS_BYTES,
+                  c = HopShape<S, 16>::LDS_BYTES;
+    return a > b ? (a > c ? a : c) : (b > c ? b : c);
+}
+
+template <class S, bool DAG, bool EPH, bool EPA, bool CG>
+__global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void multi_hop_kernel(
+    const MultiHop<S>* __restrict__ m) {
+    __shared__ __attribute__((aligned(16))) unsigned char smem[multi_lds_bytes<S>()];
+    const int n = m->n;
+    const long items = m->first[n];
+    for (long it = blockIdx.x; it < items; it += gridDim.x) {
+        int i = 0;
+        while (i + 1 < n && it >= m->first[i + 1]) ++i;
+        const HopArgs<S>& a = m->a[i];
+        if (a.done && *a.done) continue;  // this lattice has converged (uniform branch)
+        const int gx = m->gx[i];
+        const long r = it - m->first[i];
+        const int d = (int)(r / gx), bx = (int)(r - (long)d * gx);
+        switch (m->ls[i]) {
+            case 8: hop_body<S, 8, DAG, EPH, EPA, CG>(a, bx, d, gx, smem); break;
+            case 12: hop_body<S, 12, DAG, EPH, EPA, CG>(a, bx, d, gx, smem); break;
+            default: hop_body<S, 16, DAG, EPH, EPA, CG>(a, bx, d, gx, smem); break;
+        }
+        __syncthreads();  // LDS is reused by the next item
+    }
+}
+
+template <class S>
+int launch_multi_hop(const MultiHop<S>* dev, long items, bool dag, bool eph, bool epa, bool cg,
+                     hipStream_t st) {
+    if (items <= 0) return 0;
+    // persistent grid: at most 4 workgroups per CU, each walking the list
+    const long g = items < 1024 ? items : 1024;
+    dim3 grid((unsigned)g), block(256);
+#define MSPCG_MH(D, H, A, C) hipLaunchKernelGGL((multi_hop_kernel<S, D, H, A, C>), grid, block, 0, st, dev)
+    if (!dag && eph && !epa && !cg) MSPCG_MH(false, true, false, false);
+    else if (!dag && !eph && !epa && !cg) MSPCG_MH(false, false, false, false);
+    else if (dag && eph && !epa && !cg) MSPCG_MH(true, true, false, false);
+    else if (dag && !eph && !epa && cg) MSPCG_MH(true, false, false, true);
+    else if (dag && cg) MSPCG_MH(true, true, true, true);
+    else return -1;
+#undef MSPCG_MH
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
 }  // namespace mspcg

@@ -318,12 +318,14 @@ static double hop_read_sites(const Box& in, const Box& out) {
     return n;
 }
 
+// Arguments of one block-domain hop (every block in one launch) and its
+// algorithmic bytes.
 template <class S>
-static int dom_hop(mspcg_ctx* c, Field<S> out, const Box& bout, CField<S> in, const Box& bin,
-                   int out_par, bool dag, const FiveDProg& ph, const CField<S>* aux,
-                   const Box& baux, const FiveDProg& pa, double* partials, const int* done,
-                   hipStream_t st, const HopArgs<S>* cg = nullptr, const int* list = nullptr,
-                   long nlist = 0, long nread = 0) {
+static HopArgs<S> dom_hop_args(mspcg_ctx* c, Field<S> out, const Box& bout, CField<S> in,
+                               const Box& bin, int out_par, const FiveDProg& ph,
+                               const CField<S>* aux, const Box& baux, const FiveDProg& pa,
+                               double* partials, const int* done, const HopArgs<S>* cg,
+                               const int* list, long nlist, long nread, double& bytes) {
     const Domains& D = c->dom;
     HopArgs<S> a;
     memset(&a, 0, sizeof(a));
@@ -365,10 +367,22 @@ static int dom_hop(mspcg_ctx* c, Field<S> out, const Box& bout, CField<S> in, co
     double entries = nout + (list ? (double)nread : hop_read_sites(bin, bout) / 2) +
                      (aux ? box_overlap(baux, bout) / 2 : 0);
     if (cg) entries += nout * (cg->cg_x.data ? (cg->cg_first ? 3 : 4) : 1);
-    const double bytes = (double)D.ndom * c->Ls * entries * S::bytes_spinor +
-                         (double)D.ndom * nout * 8 * S::bytes_link;
+    bytes = (double)D.ndom * c->Ls * entries * S::bytes_spinor +
+            (double)D.ndom * nout * 8 * S::bytes_link;
+    return a;
+}
+
+template <class S>
+static int dom_hop(mspcg_ctx* c, Field<S> out, const Box& bout, CField<S> in, const Box& bin,
+                   int out_par, bool dag, const FiveDProg& ph, const CField<S>* aux,
+                   const Box& baux, const FiveDProg& pa, double* partials, const int* done,
+                   hipStream_t st, const HopArgs<S>* cg = nullptr, const int* list = nullptr,
+                   long nlist = 0, long nread = 0) {
+    double bytes;
+    const HopArgs<S> a = dom_hop_args<S>(c, out, bout, in, bin, out_par, ph, aux, baux, pa,
+                                         partials, done, cg, list, nlist, nread, bytes);
     Timed t(c, cg ? MSPCG_KC_HOPDOMCG : MSPCG_KC_HOPDOM, bytes, st);
-    return launch_hop<S>(a, c->Ls, D.ndom, dag, st);
+    return launch_hop<S>(a, c->Ls, c->dom.ndom, dag, st);
 }
 
 template <class S>
@@ -442,68 +456,6 @@ int block_A(mspcg_ctx* c, Field<S> w, CField<S> p, double* partials, const int* 
                       &yc, D.ybox(), P.M5dag, nullptr, done, st);
 }
 
-// One local CG step on every block with the vector updates fused into the
-// block operator: p = rho + beta p rides on t = B p (it > 0), alpha =
-// gam / |Mhat_D p|^2 per block is formed after the Mhat half, and the last
-// hop does rho -= alpha w with the per-block |rho|^2 partials
-// ([ndom][hop_grid_x(interior.Vh)]); w is never stored.  The solution update
-// z += alpha p of step it is deferred to the B kernel of step it + 1, which
-// reads the old p anyway (z = alpha p there when it + 1 == 1); the last step
-// (it == l - 1) does it in its last hop.  pq_partials receive |Mhat_D p|^2
-// laid out [ndom][hop_np].
-template <class S>
-static int block_cg_step(mspcg_ctx* c, Field<S> p, Field<S> rho, Field<S> z,
-                         const InnerScalars& sc, int it, int l, double* part, long hop_np,
-                         const int* done, hipStream_t st) {
-    const Domains& D = c->dom;
-    const int Ls = c->Ls;
-    const std::string pf = std::string("dom") + (std::is_same<S, F16>::value ? "16." : std::is_same<S, F32>::value ? "32." : "64.");
-    Field<S> t = half_field<S>(c, pf + "t", (long)D.ndom * D.interior.Vh * Ls);
-    Field<S> u = half_field<S>(c, pf + "u", (long)D.ndom * D.pad1.Vh * Ls);
-    Field<S> y = half_field<S>(c, pf + "y", (long)D.ndom * D.pad2.Vh * Ls);
-    Field<S> v = half_field<S>(c, pf + "v", (long)D.ndom * D.pad1.Vh * Ls);
-    if (!t.data || !u.data || !y.data || !v.data) return MSPCG_ENOMEM;
-    const Progs& P = c->pr;
-    FiveDProg m14;
-    memset(&m14, 0, sizeof(m14));
-    m14.scale[0] = m14.scale[1] = -0.25;
-    m14.identity = 1;
-    const CField<S> pc = cfield(p);
-    int e;
-    if (it > 0) {
-        // sc.a still holds the step length of step it - 1 here
-        if ((e = dom_fived<S>(c, t, pc, D.interior.Vh, P.B, done, st, &p, cfield(rho), sc.beta, &z,
-                              sc.a, it == 1 ? 1 : 0)))
-            return e;
-    } else if ((e = dom_fived<S>(c, t, pc, D.interior.Vh, P.B, done, st))) {
-        return e;
-    }
-    if ((e = dom_hop<S>(c, u, D.pad1, cfield(t), D.interior, 1, false, P.X, nullptr, D.interior,
-                        P.id, nullptr, done, st)))
-        return e;
-    if ((e = dom_hop<S>(c, y, D.ybox(), cfield(u), D.pad1, 0, false, m14, &pc, D.interior, P.M5,
-                        part, done, st, nullptr, D.ylist(), D.yn(), D.yread())))
-        return e;
-    hipLaunchKernelGGL(inner_alpha, dim3(D.ndom), dim3(kThreads), 0, st, sc, part, (int)hop_np,
-                       done);
-    if (last_error()) return MSPCG_EHIP;
-    if ((e = dom_hop<S>(c, v, D.pad1, cfield(y), D.ybox(), 1, true, P.Xdag, nullptr, D.interior,
-                        P.id, nullptr, done, st, nullptr, D.list_v, D.n_v, D.rd_v)))
-        return e;
-    HopArgs<S> cg;
-    memset(&cg, 0, sizeof(cg));
-    cg.cg_r = rho;
-    if (it == l - 1) cg.cg_x = z;  // earlier steps: deferred to the next B kernel
-    cg.cg_p = pc;
-    cg.cg_alpha = sc.a;
-    cg.cg_first = it == 0 ? 1 : 0;
-    const CField<S> yc = cfield(y);
-    Field<S> none;
-    memset(&none, 0, sizeof(none));
-    return dom_hop<S>(c, none, D.interior, cfield(v), D.pad1, 0, true, scaled(P.Bdag, -0.25, -0.25),
-                      &yc, D.ybox(), P.M5dag, part, done, st, &cg);
-}
-
 static InnerScalars inner_scalars(mspcg_ctx* c) {
     InnerScalars s;
     const int n = c->dom.ndom;
@@ -514,69 +466,325 @@ static InnerScalars inner_scalars(mspcg_ctx* c) {
     return s;
 }
 
-// z_e = K_l^-1 r_e (FP64 whole-lattice even fields); `done` (device flag,
-// may be null) skips the work once the outer solve has converged.
+// The local solves of one lattice: K_l^-1 r as l CG steps on every block
+// (eq. (4)), split into the pieces that several lattices can interleave
+// stage by stage.  One step:
+//   B      t = B p; p = rho + beta p rides on it (step > 0), and the solution
+//          update z += alpha p of the previous step (it reads the old p)
+//   hop 0  u = X D_h^oe t                    (odd, block widened by 1)
+//   hop 1  y = M5op p - D_h^eo u / 4 = Mhat_D p, |y|^2 = <p, A_s p> partials
+//   alpha  per block: alpha = gamma / <p, A_s p>
+//   hop 2  v = X^+ Dd^oe y                    (odd, within 1 of the block)
+//   hop 3  A_s p = M5op^+ y - B^+ Dd^eo v / 4 on the block, fused with
+//          rho -= alpha A_s p and its |rho|^2 partials (A_s p is not stored);
+//          the last step also does z += alpha p there
+//   beta   per block, for the next step
 template <class S>
-static int precond_core(mspcg_ctx* c, int l, CField<F64> r, Field<F64> z, const int* done,
-                        hipStream_t st, PrecondDots* dots = nullptr) {
+struct Local {
+    mspcg_ctx* c = nullptr;
+    Field<S> rho, p, zz, t, u, y, v;
+    InnerScalars sc;
+    long hop_np = 0, start_np = 0, upd_np = 0;
+    FiveDProg m14;
+};
+
+template <class S>
+static int local_init(mspcg_ctx* c, Local<S>& L) {
     const Domains& D = c->dom;
     const int Ls = c->Ls;
     const long nd = D.interior.Vh * Ls;  // (site, s) per domain
     const std::string pf = std::string("dom") + (std::is_same<S, F16>::value ? "16." : std::is_same<S, F32>::value ? "32." : "64.");
-    Field<S> rho = half_field<S>(c, pf + "rho", D.ndom * nd);
-    Field<S> p = half_field<S>(c, pf + "p", D.ndom * nd);
-    Field<S> zz = half_field<S>(c, pf + "z", D.ndom * nd);
-    if (!rho.data || !p.data || !zz.data) return MSPCG_ENOMEM;
-    InnerScalars sc = inner_scalars(c);
-    const long hop_np = hop_grid_x<S>(D.yout(), Ls);
+    L.c = c;
+    L.rho = half_field<S>(c, pf + "rho", D.ndom * nd);
+    L.p = half_field<S>(c, pf + "p", D.ndom * nd);
+    L.zz = half_field<S>(c, pf + "z", D.ndom * nd);
+    L.t = half_field<S>(c, pf + "t", (long)D.ndom * D.interior.Vh * Ls);
+    L.u = half_field<S>(c, pf + "u", (long)D.ndom * D.pad1.Vh * Ls);
+    L.y = half_field<S>(c, pf + "y", (long)D.ndom * D.pad2.Vh * Ls);
+    L.v = half_field<S>(c, pf + "v", (long)D.ndom * D.pad1.Vh * Ls);
+    if (!L.rho.data || !L.p.data || !L.zz.data || !L.t.data || !L.u.data || !L.y.data ||
+        !L.v.data)
+        return MSPCG_ENOMEM;
+    L.sc = inner_scalars(c);
+    if (!L.sc.gam || !L.sc.a || !L.sc.beta || !L.sc.active) return MSPCG_ENOMEM;
+    L.hop_np = hop_grid_x<S>(D.yout(), Ls);
     const int spb = kThreads / Ls;
-    const long start_np = (D.interior.Vh + spb - 1) / spb;
+    L.start_np = (D.interior.Vh + spb - 1) / spb;
+    // partials of the fused update: one per workgroup of the interior hop
+    L.upd_np = hop_grid_x<S>(D.interior.Vh, Ls);
     const long vec_np = (nd + kThreads - 1) / kThreads;
-    long need = hop_np > start_np ? hop_np : start_np;
+    long need = L.hop_np > L.start_np ? L.hop_np : L.start_np;
     if (vec_np > need) need = vec_np;
     int e = ensure_partials(c, (size_t)(D.ndom * need + 64));
     if (e) return e;
-    double* part = c->partials;
+    memset(&L.m14, 0, sizeof(L.m14));
+    L.m14.scale[0] = L.m14.scale[1] = -0.25;
+    L.m14.identity = 1;
+    return 0;
+}
+
+// rho = p = r on every block, gamma = |rho|^2 per block
+template <class S>
+static int local_start(Local<S>& L, CField<F64> r, const int* done, hipStream_t st) {
+    mspcg_ctx* c = L.c;
+    const Domains& D = c->dom;
+    const int Ls = c->Ls;
+    const long nd = D.interior.Vh * Ls;
     DomGeom g;
     for (int m = 0; m < 4; ++m) {
         g.L[m] = c->L[m];
         g.blk[m] = D.blk[m];
         g.nb[m] = D.nb[m];
     }
-    {
-        Timed t(c, MSPCG_KC_BLAS, (double)D.ndom * nd * (192.0 + 2 * S::bytes_spinor), st);
-        hipLaunchKernelGGL(inner_start_kernel<S>, dim3((unsigned)start_np, D.ndom), dim3(spb * Ls),
-                           0, st, r, rho, p, g, Ls, D.interior.Vh, part, done);
-        if (last_error()) return MSPCG_EHIP;
-        hipLaunchKernelGGL(inner_start_scalars, dim3(D.ndom), dim3(kThreads), 0, st, sc, part,
-                           (int)start_np, done);
-        if (last_error()) return MSPCG_EHIP;
-    }
-    // partials of the fused update: one per workgroup of the interior hop
-    const long upd_np = hop_grid_x<S>(D.interior.Vh, Ls);
-    for (int it = 0; it < l; ++it) {
-        if ((e = block_cg_step<S>(c, p, rho, zz, sc, it, l, part, hop_np, done, st))) return e;
-        if (it + 1 < l) {
-            hipLaunchKernelGGL(inner_beta, dim3(D.ndom), dim3(kThreads), 0, st, sc, part,
-                               (int)upd_np, done);
-            if (last_error()) return MSPCG_EHIP;
-        }
-    }
-    // z written in FP64 from the domain copy (+ r and q read for the dots)
+    const int spb = kThreads / Ls;
+    Timed t(c, MSPCG_KC_BLAS, (double)D.ndom * nd * (192.0 + 2 * S::bytes_spinor), st);
+    hipLaunchKernelGGL(inner_start_kernel<S>, dim3((unsigned)L.start_np, D.ndom), dim3(spb * Ls), 0,
+                       st, r, L.rho, L.p, g, Ls, D.interior.Vh, c->partials, done);
+    if (last_error()) return MSPCG_EHIP;
+    hipLaunchKernelGGL(inner_start_scalars, dim3(D.ndom), dim3(kThreads), 0, st, L.sc, c->partials,
+                       (int)L.start_np, done);
+    return last_error();
+}
+
+template <class S>
+static int local_B(Local<S>& L, int it, const int* done, hipStream_t st) {
+    mspcg_ctx* c = L.c;
+    const Domains& D = c->dom;
+    const CField<S> pc = cfield(L.p);
+    if (it > 0)  // L.sc.a still holds the step length of step it - 1 here
+        return dom_fived<S>(c, L.t, pc, D.interior.Vh, c->pr.B, done, st, &L.p, cfield(L.rho),
+                            L.sc.beta, &L.zz, L.sc.a, it == 1 ? 1 : 0);
+    return dom_fived<S>(c, L.t, pc, D.interior.Vh, c->pr.B, done, st);
+}
+
+// Arguments of hop k (0..3, see Local) of step it of l; dag: the dagger hop
+template <class S>
+static HopArgs<S> local_hop(Local<S>& L, int k, int it, int l, const int* done, double& bytes,
+                            bool& dag) {
+    mspcg_ctx* c = L.c;
+    const Domains& D = c->dom;
+    const Progs& P = c->pr;
+    const CField<S> pc = cfield(L.p);
+    const CField<S> yc = cfield(L.y);
+    double* part = c->partials;
+    dag = k >= 2;
+    if (k == 0)
+        return dom_hop_args<S>(c, L.u, D.pad1, cfield(L.t), D.interior, 1, P.X, nullptr,
+                               D.interior, P.id, nullptr, done, nullptr, nullptr, 0, 0, bytes);
+    if (k == 1)
+        return dom_hop_args<S>(c, L.y, D.ybox(), cfield(L.u), D.pad1, 0, L.m14, &pc, D.interior,
+                               P.M5, part, done, nullptr, D.ylist(), D.yn(), D.yread(), bytes);
+    if (k == 2)
+        return dom_hop_args<S>(c, L.v, D.pad1, yc, D.ybox(), 1, P.Xdag, nullptr, D.interior, P.id,
+                               nullptr, done, nullptr, D.list_v, D.n_v, D.rd_v, bytes);
+    HopArgs<S> cg;
+    memset(&cg, 0, sizeof(cg));
+    cg.cg_r = L.rho;
+    if (it == l - 1) cg.cg_x = L.zz;  // earlier steps: deferred to the next B kernel
+    cg.cg_p = pc;
+    cg.cg_alpha = L.sc.a;
+    cg.cg_first = it == 0 ? 1 : 0;
+    Field<S> none;
+    memset(&none, 0, sizeof(none));
+    return dom_hop_args<S>(c, none, D.interior, cfield(L.v), D.pad1, 0,
+                           scaled(P.Bdag, -0.25, -0.25), &yc, D.ybox(), P.M5dag, part, done, &cg,
+                           nullptr, 0, 0, bytes);
+}
+
+template <class S>
+static int local_alpha(Local<S>& L, const int* done, hipStream_t st) {
+    hipLaunchKernelGGL(inner_alpha, dim3(L.c->dom.ndom), dim3(kThreads), 0, st, L.sc,
+                       L.c->partials, (int)L.hop_np, done);
+    return last_error();
+}
+
+template <class S>
+static int local_beta(Local<S>& L, const int* done, hipStream_t st) {
+    hipLaunchKernelGGL(inner_beta, dim3(L.c->dom.ndom), dim3(kThreads), 0, st, L.sc,
+                       L.c->partials, (int)L.upd_np, done);
+    return last_error();
+}
+
+// z written in FP64 from the domain copy (with the flexible-beta dots)
+template <class S>
+static int local_finish(Local<S>& L, int l, Field<F64> z, PrecondDots* dots, hipStream_t st) {
+    mspcg_ctx* c = L.c;
+    const Domains& D = c->dom;
+    const int Ls = c->Ls;
+    const long nd = D.interior.Vh * Ls;
     Timed t(c, MSPCG_KC_BLAS,
             (double)D.ndom * nd * (192.0 + S::bytes_spinor + (dots && l > 0 ? 2 * 192.0 : 0.0)), st);
-    if (l == 0) {
-        return launch_zero(z.data, c->Nh, st) ? MSPCG_EHIP : 0;
-    }
+    if (l == 0) return launch_zero(z.data, c->Nh, st) ? MSPCG_EHIP : 0;
     if (dots) {
         // z and the workgroup partials of Re<z, r>, Re<z, q> in one pass
-        dots->np = launch_domain_to_global_dots<S>(cfield(zz), z, dots->r, dots->q, c->L, D.blk,
+        dots->np = launch_domain_to_global_dots<S>(cfield(L.zz), z, dots->r, dots->q, c->L, D.blk,
                                                    D.nb, Ls, c->partials, st);
         return dots->np < 0 ? MSPCG_EHIP : 0;
     }
-    if (launch_domain_to_global<S, F64>(cfield(zz), z, c->L, D.blk, D.nb, Ls, 0, st))
+    if (launch_domain_to_global<S, F64>(cfield(L.zz), z, c->L, D.blk, D.nb, Ls, 0, st))
         return MSPCG_EHIP;
     return 0;
+}
+
+// z_e = K_l^-1 r_e (FP64 whole-lattice even fields); `done` (device flag,
+// may be null) skips the work once the outer solve has converged.
+template <class S>
+static int precond_core(mspcg_ctx* c, int l, CField<F64> r, Field<F64> z, const int* done,
+                        hipStream_t st, PrecondDots* dots = nullptr) {
+    Local<S> L;
+    int e;
+    if ((e = local_init<S>(c, L))) return e;
+    if ((e = local_start<S>(L, r, done, st))) return e;
+    for (int it = 0; it < l; ++it) {
+        if ((e = local_B<S>(L, it, done, st))) return e;
+        for (int k = 0; k < 4; ++k) {
+            double bytes;
+            bool dag;
+            const HopArgs<S> a = local_hop<S>(L, k, it, l, done, bytes, dag);
+            {
+                Timed t(c, k == 3 ? MSPCG_KC_HOPDOMCG : MSPCG_KC_HOPDOM, bytes, st);
+                if (launch_hop<S>(a, c->Ls, c->dom.ndom, dag, st)) return MSPCG_EHIP;
+            }
+            if (k == 1 && (e = local_alpha<S>(L, done, st))) return e;
+        }
+        if (it + 1 < l && (e = local_beta<S>(L, done, st))) return e;
+    }
+    return local_finish<S>(L, l, z, dots, st);
+}
+
+// Local solves of several lattices interleaved stage by stage; with `multi`
+// every block-hop stage of all lattices is one persistent multi-lattice
+// launch (MultiHop), otherwise one launch per lattice.
+template <class S>
+struct BatchPrecondImpl : BatchPrecond {
+    std::vector<Local<S>> L;
+    std::vector<const int*> done;
+    // stages 0..2 (hops u, y, v), then hop 3 for (first step, last step) =
+    // (0,0) (0,1) (1,0) (1,1): descriptors in device memory
+    MultiHop<S>* dev = nullptr;
+    long items[7] = {};
+    bool dag[7] = {}, eph[7] = {}, epa[7] = {}, cgf[7] = {};
+    ~BatchPrecondImpl() override {
+        if (dev) (void)hipFree(dev);
+    }
+    static bool chain(const FiveDProg& P) { return !P.identity && !(P.nsteps == 1 && P.kind[0] == STEP_BIDI); }
+    int build(int l) {
+        const int n = (int)L.size();
+        std::vector<MultiHop<S>> h(7);
+        for (int k = 0; k < 7; ++k) {
+            memset(&h[k], 0, sizeof(MultiHop<S>));
+            const int stage = k < 3 ? k : 3;
+            int it = 0;
+            if (k >= 3) {
+                // a step with the wanted (first, last) flags, if l has one
+                const bool want_first = ((k - 3) >> 1) & 1, want_last = (k - 3) & 1;
+                it = want_first ? 0 : (want_last ? l - 1 : 1);
+                if (it >= l || (it == 0) != want_first || (it == l - 1) != want_last) {
+                    items[k] = -1;
+                    continue;
+                }
+            }
+            long first = 0;
+            for (int i = 0; i < n; ++i) {
+                double bytes;
+                bool dg;
+                const HopArgs<S> a = local_hop<S>(L[i], stage, it, l, done[i], bytes, dg);
+                const long nout = a.site_list ? a.n_list : a.g.out.Vh;
+                const bool e1 = chain(a.ph), e2 = a.has_aux && chain(a.pa);
+                if (i == 0) {
+                    dag[k] = dg;
+                    eph[k] = e1;
+                    epa[k] = e2;
+                    cgf[k] = a.cg_r.data != nullptr;
+                } else if (e1 != eph[k] || e2 != epa[k]) {
+                    return MSPCG_EUNSUPPORTED;  // lattices need different kernel variants
+                }
+                h[k].a[i] = a;
+                h[k].ls[i] = L[i].c->Ls;
+                h[k].gx[i] = (int)hop_grid_x<S>(nout, L[i].c->Ls);
+                h[k].first[i] = first;
+                first += (long)L[i].c->dom.ndom * h[k].gx[i];
+            }
+            h[k].first[n] = first;
+            h[k].n = n;
+            items[k] = first;
+        }
+        if (hipMalloc(&dev, 7 * sizeof(MultiHop<S>)) != hipSuccess) return MSPCG_ENOMEM;
+        if (hipMemcpy(dev, h.data(), 7 * sizeof(MultiHop<S>), hipMemcpyHostToDevice) != hipSuccess)
+            return MSPCG_EHIP;
+        return 0;
+    }
+    int hop(int k, int it, int l, hipStream_t st) {
+        if (multi) {
+            const int j = k < 3 ? k : 3 + 2 * (it == 0) + (it == l - 1);
+            if (items[j] < 0) return MSPCG_EHIP;
+            return launch_multi_hop<S>(dev + j, items[j], dag[j], eph[j], epa[j], cgf[j], st)
+                       ? MSPCG_EHIP
+                       : 0;
+        }
+        for (size_t i = 0; i < L.size(); ++i) {
+            double bytes;
+            bool dg;
+            const HopArgs<S> a = local_hop<S>(L[i], k, it, l, done[i], bytes, dg);
+            if (launch_hop<S>(a, L[i].c->Ls, L[i].c->dom.ndom, dg, st)) return MSPCG_EHIP;
+        }
+        return 0;
+    }
+    int apply(int l, const CField<F64>* r, const Field<F64>* z, PrecondDots* dots,
+              hipStream_t st) override {
+        const size_t n = L.size();
+        int e;
+        for (size_t i = 0; i < n; ++i)
+            if ((e = local_start<S>(L[i], r[i], done[i], st))) return e;
+        for (int it = 0; it < l; ++it) {
+            for (size_t i = 0; i < n; ++i)
+                if ((e = local_B<S>(L[i], it, done[i], st))) return e;
+            for (int k = 0; k < 4; ++k) {
+                if ((e = hop(k, it, l, st))) return e;
+                if (k == 1)
+                    for (size_t i = 0; i < n; ++i)
+                        if ((e = local_alpha<S>(L[i], done[i], st))) return e;
+            }
+            if (it + 1 < l)
+                for (size_t i = 0; i < n; ++i)
+                    if ((e = local_beta<S>(L[i], done[i], st))) return e;
+        }
+        for (size_t i = 0; i < n; ++i)
+            if ((e = local_finish<S>(L[i], l, z[i], dots ? dots + i : nullptr, st))) return e;
+        return 0;
+    }
+};
+
+template <class S>
+static int make_batch_impl(mspcg_ctx* const* cs, int n, int l, const int* const* done,
+                           bool multi, std::unique_ptr<BatchPrecond>& out) {
+    std::unique_ptr<BatchPrecondImpl<S>> b(new BatchPrecondImpl<S>());
+    b->L.resize(n);
+    b->done.assign(done, done + n);
+    int e;
+    for (int i = 0; i < n; ++i)
+        if ((e = local_init<S>(cs[i], b->L[i]))) return e;
+    if (multi) {
+        bool ok = n <= kMaxBatch && l > 0;
+        for (int i = 0; i < n && ok; ++i) ok = multi_hop_ls(cs[i]->Ls);
+        if (ok) {
+            e = b->build(l);
+            if (e && e != MSPCG_EUNSUPPORTED) return e;
+            b->multi = e == 0;
+        }
+    }
+    out = std::move(b);
+    return 0;
+}
+
+int make_batch_precond(mspcg_ctx* const* cs, int n, int prec, int l, const int* const* done,
+                       bool multi, std::unique_ptr<BatchPrecond>& out) {
+    switch (prec) {
+        case MSPCG_FP16: return make_batch_impl<F16>(cs, n, l, done, multi, out);
+        case MSPCG_FP32: return make_batch_impl<F32>(cs, n, l, done, multi, out);
+        case MSPCG_FP64: return make_batch_impl<F64>(cs, n, l, done, multi, out);
+        default: return MSPCG_EINVAL;
+    }
 }
 
 size_t precond_partials_need(mspcg_ctx* c) {

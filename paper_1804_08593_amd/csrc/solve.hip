@@ -103,6 +103,12 @@ struct Solver {
     virtual int iterate(hipStream_t st) = 0;
     virtual int after_poll(hipStream_t st) = 0;
     virtual int check_default() const = 0;
+    // MSPCG solvers in a batch split one iteration around the local solves,
+    // which the batch runs for every lattice together (BatchPrecond)
+    virtual bool batch_mspcg() const { return false; }
+    virtual int iterate_pre(hipStream_t) { return MSPCG_EUNSUPPORTED; }
+    virtual int iterate_post(hipStream_t, long) { return MSPCG_EUNSUPPORTED; }
+    virtual void batch_io(CField<F64>&, Field<F64>&, CField<F64>&) {}
     int rc() const {
         if (breakdown) return MSPCG_EBREAKDOWN;
         return converged ? MSPCG_OK : MSPCG_ENOCONV;
@@ -268,17 +274,31 @@ struct MSPCGSolver : Solver {
     // z = K r ; flexible beta from <z, r> and <z, q>
     int iterate(hipStream_t st) override {
         int e;
-        if ((e = cg_step<F64>(c, x, r, pp, q, cfield(z), true, true, &c->sc->done, st))) return e;
-        if (launch_cg_beta(c->sc, c->partials, (int)nph, c->hist, cap, st)) return MSPCG_EHIP;
+        if ((e = iterate_pre(st))) return e;
         PrecondDots dots{cfield(r), cfield(q), 0};
         if ((e = precond_apply_flag<S>(c, l, cfield(r), z, &c->sc->done, st, &dots))) return e;
-        long np = dots.np;
+        return iterate_post(st, dots.np);
+    }
+    bool batch_mspcg() const override { return true; }
+    int iterate_pre(hipStream_t st) override {
+        int e;
+        if ((e = cg_step<F64>(c, x, r, pp, q, cfield(z), true, true, &c->sc->done, st))) return e;
+        if (launch_cg_beta(c->sc, c->partials, (int)nph, c->hist, cap, st)) return MSPCG_EHIP;
+        return 0;
+    }
+    // np: partials of Re<z, r>, Re<z, q> left by the local solves (0: form them)
+    int iterate_post(hipStream_t st, long np) override {
         if (np == 0) {
             if (launch_dot2(z.data, r.data, q.data, c->Nh, c->partials, npb, st)) return MSPCG_EHIP;
             np = npb;
         }
         if (launch_fpcg_beta(c->sc, c->partials, (int)np, st)) return MSPCG_EHIP;
         return 0;
+    }
+    void batch_io(CField<F64>& r_, Field<F64>& z_, CField<F64>& q_) override {
+        r_ = cfield(r);
+        z_ = z;
+        q_ = cfield(q);
     }
     int after_poll(hipStream_t st) override {
         int e;
@@ -687,6 +707,8 @@ int solve_batch(mspcg_ctx* const* cs, int n, const void* const* b, void* const* 
     int rc = MSPCG_OK;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::unique_ptr<BatchPrecond> bprec;
+    bool batch_multi = false;
     auto body = [&]() -> int {
         for (int i = 0; i < n; ++i) {
             mspcg_ctx* c = cs[i];
@@ -713,16 +735,56 @@ int solve_batch(mspcg_ctx* const* cs, int n, const void* const* b, void* const* 
             if ((e = S.init(st))) return e;
             if (S.s.done && (e = S.after_poll(st))) return e;
         }
-        // one eager iteration creates every lazily allocated buffer before capture
+        // MSPCG: the local solves of all lattices run together, every block-hop
+        // stage as one persistent multi-lattice launch (batch_kernels == 0)
+        std::vector<int> act;  // systems with a nonzero right-hand side
         for (int i = 0; i < n; ++i)
-            if (!sv[i]->finished && !sv[i]->s.done && (e = sv[i]->iterate(st))) return e;
+            if (pbs[i].bb != 0.0) act.push_back(i);
+        bool together = p->solver == MSPCG_SOLVER_MSPCG && !act.empty();
+        for (int i : act) together = together && sv[i]->batch_mspcg();
+        std::vector<CField<F64>> rr(act.size()), qq(act.size());
+        std::vector<Field<F64>> zz(act.size());
+        std::vector<PrecondDots> dots(act.size());
+        if (together) {
+            std::vector<mspcg_ctx*> ac;
+            std::vector<const int*> dn;
+            for (size_t j = 0; j < act.size(); ++j) {
+                const int i = act[j];
+                sv[i]->batch_io(rr[j], zz[j], qq[j]);
+                ac.push_back(cs[i]);
+                dn.push_back(&cs[i]->sc->done);
+            }
+            if ((e = make_batch_precond(ac.data(), (int)ac.size(), ps[act[0]].inner_prec,
+                                        ps[act[0]].inner_iters, dn.data(),
+                                        p->batch_kernels == 0, bprec)))
+                return e;
+            batch_multi = bprec->multi;
+        }
+        auto iterate_all = [&](bool eager) -> int {
+            if (!together) {
+                for (int i = 0; i < n; ++i) {
+                    Solver& S = *sv[i];
+                    if (S.bb == 0.0 || (eager && (S.finished || S.s.done))) continue;
+                    if ((e = S.iterate(st))) return e;
+                }
+                return 0;
+            }
+            for (int i : act)
+                if ((e = sv[i]->iterate_pre(st))) return e;
+            for (size_t j = 0; j < act.size(); ++j) dots[j] = PrecondDots{rr[j], qq[j], 0};
+            if ((e = bprec->apply(ps[act[0]].inner_iters, rr.data(), zz.data(), dots.data(), st)))
+                return e;
+            for (size_t j = 0; j < act.size(); ++j)
+                if ((e = sv[act[j]]->iterate_post(st, dots[j].np))) return e;
+            return 0;
+        };
+        // one eager iteration creates every lazily allocated buffer before capture
+        if ((e = iterate_all(true))) return e;
         MSPCG_HIP(hipStreamSynchronize(st));
         MSPCG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        for (int i = 0; i < n; ++i) {
-            if ((e = sv[i]->bb != 0.0 ? sv[i]->iterate(st) : 0)) {
-                (void)hipStreamEndCapture(st, &graph);
-                return e;
-            }
+        if ((e = iterate_all(false))) {
+            (void)hipStreamEndCapture(st, &graph);
+            return e;
         }
         MSPCG_HIP(hipStreamEndCapture(st, &graph));
         MSPCG_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
@@ -768,6 +830,7 @@ int solve_batch(mspcg_ctx* const* cs, int n, const void* const* b, void* const* 
         std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
     for (int i = 0; i < n && stats; ++i) {
         stats[i].seconds = secs;
+        stats[i].batch_persistent = batch_multi ? 1 : 0;
         clear_timing(stats + i);
     }
     (void)hipEventDestroy(ev);

@@ -63,7 +63,7 @@ class SolveParams(ctypes.Structure):
                 ("use_x0", ctypes.c_int), ("blocking", Blocking), ("inner_iters", ctypes.c_int),
                 ("inner_prec", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("delta", ctypes.c_double), ("timing", ctypes.c_int),
-                ("rhs_normal", ctypes.c_int)]
+                ("rhs_normal", ctypes.c_int), ("batch_kernels", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
@@ -76,7 +76,8 @@ class SolveStats(ctypes.Structure):
                 ("kernel_launches", ctypes.c_long * KC_COUNT),
                 ("kernel_bytes", ctypes.c_double * KC_COUNT),
                 ("cg_coef", ctypes.POINTER(ctypes.c_double)),
-                ("cg_coef_cap", ctypes.c_int), ("cg_coef_len", ctypes.c_int)]
+                ("cg_coef_cap", ctypes.c_int), ("cg_coef_len", ctypes.c_int),
+                ("batch_persistent", ctypes.c_int)]
 
 
 _lib = None
@@ -152,7 +153,7 @@ def _ptr(t):
 
 def make_params(tol=1e-10, maxiter=10000, solver=SOLVER_CG, use_x0=False, block=(0, 0, 0, 0),
                 pad=2, inner_iters=6, inner_prec=FP16, check_every=0, delta=0.1,
-                timing=False, rhs_normal=False, form=FORM_DOMAIN) -> SolveParams:
+                timing=False, rhs_normal=False, form=FORM_DOMAIN, batch_kernels=0) -> SolveParams:
     p = SolveParams()
     p.tol, p.maxiter, p.solver, p.use_x0 = float(tol), int(maxiter), int(solver), int(use_x0)
     for i in range(4):
@@ -162,6 +163,7 @@ def make_params(tol=1e-10, maxiter=10000, solver=SOLVER_CG, use_x0=False, block=
     p.inner_iters, p.inner_prec = int(inner_iters), int(inner_prec)
     p.check_every, p.delta, p.timing = int(check_every), float(delta), int(timing)
     p.rhs_normal = int(bool(rhs_normal))
+    p.batch_kernels = int(batch_kernels)
     return p
 
 
@@ -328,6 +330,7 @@ def stats_dict(st: SolveStats, hist=None, rc=OK, coef=None) -> dict:
         "converged": bool(st.converged),
         "true_rel_resid": st.true_rel_resid,
         "seconds": st.seconds,
+        "batch_persistent": bool(st.batch_persistent),
         "kernel_ms": {KC_NAMES[i]: st.kernel_ms[i] for i in range(KC_COUNT)},
         "kernel_launches": {KC_NAMES[i]: int(st.kernel_launches[i]) for i in range(KC_COUNT)},
         "kernel_bytes": {KC_NAMES[i]: st.kernel_bytes[i] for i in range(KC_COUNT)},

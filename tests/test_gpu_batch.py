@@ -65,6 +65,42 @@ def test_batch_equals_individual_solves(solver):
         torch.cuda.synchronize()
 
 
+# Ls 8, 12 and 16: every block-hop stage of the three lattices' local solves
+# runs as one persistent multi-lattice launch
+MULTI = [((8, 4, 4, 8), 8, 0.05, (4, 4, 4, 4)), ((4, 4, 4, 8), 12, 0.01, (4, 4, 4, 4)),
+         ((8, 8, 4, 8), 16, 0.1, (4, 4, 4, 4))]
+
+
+def test_persistent_multi_lattice_launch_matches_per_lattice_launches():
+    sys = [_make(d, Ls, mf, 0.25, 80 + i, 90 + i, blk) for i, (d, Ls, mf, blk) in enumerate(MULTI)]
+    out = {}
+    for kern in (0, 1):
+        prm = mspcg.make_params(tol=1e-10, maxiter=2000, solver=mspcg.SOLVER_MSPCG,
+                                inner_iters=4, inner_prec=mspcg.FP16, batch_kernels=kern)
+        xs = [torch.zeros_like(b) for _, _, b in sys]
+        sts = mspcg.solve_batch([c for c, _, _ in sys], [b for _, _, b in sys], xs, prm,
+                                history=2000)
+        out[kern] = (xs, sts)
+        for st in sts:
+            assert st["converged"] and st["true_rel_resid"] <= 1e-10
+            assert st["batch_persistent"] == (kern == 0)
+    bitwise = True
+    for i, (d, Ls, mf, blk) in enumerate(MULTI):
+        (xa, sa), (xb, sb) = (out[0][0][i], out[0][1][i]), (out[1][0][i], out[1][1][i])
+        say(f"lattice {d} Ls={Ls}: persistent {sa['outer_iters']} it, per-lattice "
+            f"{sb['outer_iters']} it")
+        assert sa["outer_iters"] == sb["outer_iters"]
+        assert np.allclose(sa["history"], sb["history"], rtol=1e-9, atol=0)
+        assert relerr(host(xa), host(xb)) <= 1e-12
+        bitwise = bitwise and torch.equal(xa, xb)
+        # against the oracle
+        act = O.Action(d, Ls, 1.8, mf, 1.5, 0.5)
+        _, bhat = O.prepare(act, sys[i][1], host(sys[i][2]))
+        r = bhat - O.normal(act, sys[i][1], O.parity_mask(act, host(xa), 0))
+        assert np.sqrt(O.norm2(r) / O.norm2(bhat)) <= 1e-10 * 1.01
+    say(f"persistent vs per-lattice launches bitwise identical: {bitwise}")
+
+
 C4_SHAPES = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 16), (12, 12, 12, 24),
              (16, 16, 16, 32), (20, 20, 20, 20)]
 C4_LSMF = [(8, 0.05), (12, 0.01), (16, 0.05), (8, 0.01), (12, 0.05), (16, 0.01)]
@@ -93,6 +129,8 @@ def test_config4_six_uneven_lattices(c4):
     for (ctx, U, b, mf), x, st in zip(sys, xs, sts):
         say(f"  {ctx.dims} Ls={ctx.Ls}: outer {st['outer_iters']} resid {st['true_rel_resid']:.2e}")
         assert st["converged"] and st["true_rel_resid"] <= 1e-10
+        assert st["batch_persistent"]  # one persistent launch per block-hop stage
+    say(f"  batched solve {sts[0]['seconds']:.3f} s")
 
 
 @pytest.mark.parametrize("i", range(len(C4_SHAPES)))

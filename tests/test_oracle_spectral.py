@@ -55,3 +55,13 @@ def test_ritz_values_from_oracle_cg():
     _, info2 = O.mspcg(act, U, bhat, (2, 2, 2, 2), 60, tol=1e-12)
     r2 = SP.ritz_from_coef(info2.coef)
     assert r2[0] >= ev[0] * (1 - 1e-6) and r2[-1] <= ev[-1] * (1 + 1e-6)
+
+
+def test_dense_split_block_from_schur_matrix():
+    """The split block built from the dense Schur matrix equals the oracle's
+    split block operator (two constructions)."""
+    act, U = _tiny()
+    A = SP.dense_A(act, U)
+    K = SP.dense_K(act, U, A, (2, 2, 2, 2), "split")
+    Kop = SP.dense_even(act, lambda v: O.block_precond_op(act, U, v, (2, 2, 2, 2), "split"))
+    assert np.allclose(K, Kop, atol=1e-13)
