@@ -40,6 +40,8 @@ WORKLOADS = {
                                    eps=0.2, block=(8, 8, 8, 8), gseed=1002, rseed=2002),
     "dwf_moebius_32c64_ls12": dict(dims=(32, 32, 32, 64), Ls=12, M5=1.8, mf=0.01, b=1.5, c=0.5,
                                    eps=0.2, block=(16, 16, 16, 32), gseed=1006, rseed=2006),
+    "dwf_moebius_16c32_ls12": dict(dims=(16, 16, 16, 32), Ls=12, M5=1.8, mf=0.01, b=1.5, c=0.5,
+                                   eps=0.2, block=(8, 8, 8, 16), gseed=1005, rseed=2005),
 }
 DEFAULT = "dwf_moebius_24c48_ls16"
 
@@ -230,6 +232,46 @@ def c5b_dslash(args, log):
     return res
 
 
+def force_bytes(w, with_grad=True):
+    """Algorithmic HBM bytes of the force kernel: the four FP64 half spinors
+    a_e, a_o, b_e, b_o once, the forward links once, F (and the gradient)
+    written once, 144 B per 3x3 complex matrix."""
+    V4 = int(np.prod(w["dims"]))
+    return 4 * (V4 // 2) * w["Ls"] * 192 + 4 * V4 * 144 * (3 if with_grad else 2)
+
+
+def force_c5a(args, log, calls=10):
+    """HMC force on 16^3x32, Ls=12 (mspcg_force: two packs, B X, two hops,
+    the force kernel; F and the gradient both written): wall time per call
+    (each call ends with a stream synchronisation)."""
+    import torch
+
+    from paper_1804_08593_amd import mspcg, synth
+
+    w = WORKLOADS["dwf_moebius_16c32_ls12"]
+    U = synth.gauge_field(w["dims"], w["eps"], w["gseed"])
+    ctx = mspcg.Context(w["dims"], w["Ls"], w["M5"], w["mf"], w["b"], w["c"])
+    ctx.load_gauge(torch.from_numpy(U).cuda())
+    X = torch.from_numpy(synth.fermion_field(w["dims"], w["Ls"], w["rseed"])).cuda()
+    Y = torch.from_numpy(synth.fermion_field(w["dims"], w["Ls"], w["rseed"] + 1)).cuda()
+    F = torch.empty((4,) + tuple(reversed(w["dims"])) + (3, 3), dtype=torch.complex128,
+                    device="cuda")
+    G = torch.empty_like(F)
+    ctx.force(X, Y, F, G)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        ctx.force(X, Y, F, G)
+    ms = 1e3 * (time.perf_counter() - t0) / calls
+    res = {"workload": "dwf_moebius_16c32_ls12", "dims": list(w["dims"]), "Ls": w["Ls"],
+           "calls": calls, "ms_per_call": round(ms, 4),
+           "force_kernel_bytes": force_bytes(w)}
+    log(f"[bench] 16^3x32 force: {res['ms_per_call']} ms per call")
+    del ctx, X, Y, F, G
+    torch.cuda.empty_cache()
+    return res
+
+
 # six uneven lattices solved together: dims, Ls, mf (b=1.5, c=0.5, M5=1.8,
 # links exp(0.25 i H)); gauge seed 1040 + i, source seed 2040 + i
 BATCH = [((8, 8, 8, 8), 8, 0.05), ((12, 12, 12, 12), 12, 0.01), ((16, 16, 16, 16), 16, 0.05),
@@ -328,6 +370,9 @@ def main():
                     help="time the oracle's 16^4x12 CG solve to the end (about a minute)")
     ap.add_argument("--no-c5b", action="store_true", help="skip the 32^3x64 dslash leg")
     ap.add_argument("--no-fp64-inner", action="store_true")
+    ap.add_argument("--no-force", action="store_true", help="skip the 16^3x32 force leg")
+    ap.add_argument("--force-only", action="store_true",
+                    help="run only the 16^3x32 force leg and print its JSON line")
     ap.add_argument("--batch", action="store_true",
                     help="instead of the bench line: the six uneven lattices solved together "
                          "with persistent multi-lattice block hops and with one launch per "
@@ -362,6 +407,10 @@ def main():
 
     if args.batch:
         batch_compare(args)
+        return
+    if args.force_only:
+        print(json.dumps(force_c5a(args, lambda *a: print(*a, file=sys.stderr, flush=True))),
+              flush=True)
         return
     w = WORKLOADS[args.workload]
     dims, Ls = w["dims"], w["Ls"]
@@ -521,6 +570,8 @@ def main():
                                     "seconds": round(s64["seconds"], 4),
                                     "true_rel_resid": s64["true_rel_resid"]}
         log(f"[bench] FP64-inner MSPCG: {s64['outer_iters']} outer iterations")
+    if not args.no_force:
+        line["c5a_force"] = force_c5a(args, log)
     if not args.no_c5b:
         line["c5b_dslash"] = c5b_dslash(args, log)
         log(f"[bench] 32^3x64 dslash: {line['c5b_dslash'].get('hop64')}")

@@ -10,7 +10,19 @@
 //   (TA: traceless part), and the gradient with respect to the unconstrained
 //   complex link (dS = Re sum conj(g) dU) is g = -eta (P^+ + Q).
 // eta (the antiperiodic-time sign) is already folded into the stored links.
-// One thread per (link, direction); the s and spin sums run in the thread.
+// (1 -+ g_mu) = W W^+ with W = [1; -+e_mu^+] (chiral basis), so every spin
+// sum above contracts two half spinors: P = sum_s h-(b(x+mu)) h-(a(x))^+ and
+// Q = sum_s h+(b(x)) h+(a(x+mu))^+ with h_sig(psi) = psi_up + sig e_mu psi_dn
+// (two spin rows of three colours each).
+// A workgroup of one wave takes 64/Ls sites, one lane per (site, s).  For
+// P, every lane keeps its a(x) in registers and, per direction, loads
+// b(x+mu) and forms its slice's 3x3 partial; neighbouring slices are added
+// across lanes, the pair sums go through LDS and are summed over s in a
+// fixed order by one lane per (site, entry).  Q the
+// same way with b(x) kept.  Then one lane per (site, direction, entry)
+// writes that entry of F and of the gradient.  Spinor loads are 16-byte chunks of
+// consecutive s, as in the hop, and each field is read once per direction
+// that needs it.
 #include <string.h>
 
 #include "ctx.h"
@@ -19,9 +31,11 @@ namespace mspcg {
 
 namespace {
 
-// h = psi_up + sig e_mu psi_dn ; lower = sig e_mu^+ h  (chiral basis, see hop.hip)
+// h = psi_up + SIG e_mu psi_dn (chiral basis, see hop.hip): the two spin rows
+// that (1 + SIG g_mu) keeps
 template <int SIG>
-__device__ __forceinline__ void proj_full(int mu, const cx<double> (&p)[12], cx<double> (&o)[12]) {
+__device__ __forceinline__ void proj_half(int mu, const cx<double> (&p)[12], cx<double> (&h)[6]) {
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
         const cx<double> u0 = p[c], u1 = p[3 + c], d0 = p[6 + c], d1 = p[9 + c];
         cx<double> h0, h1;
@@ -38,25 +52,28 @@ __device__ __forceinline__ void proj_full(int mu, const cx<double> (&p)[12], cx<
             h0 = {u0.re + SIG * d0.re, u0.im + SIG * d0.im};
             h1 = {u1.re + SIG * d1.re, u1.im + SIG * d1.im};
         }
-        o[c] = h0;
-        o[3 + c] = h1;
-        cx<double> l0, l1;  // e^+ h
-        if (mu == 0) {
-            l0 = {-h1.im, h1.re};
-            l1 = {-h0.im, h0.re};
-        } else if (mu == 1) {
-            l0 = h1;
-            l1 = {-h0.re, -h0.im};
-        } else if (mu == 2) {
-            l0 = {-h0.im, h0.re};
-            l1 = {h1.im, -h1.re};
-        } else {
-            l0 = h0;
-            l1 = h1;
-        }
-        o[6 + c] = {SIG * l0.re, SIG * l0.im};
-        o[9 + c] = {SIG * l1.re, SIG * l1.im};
+        h[c] = h0;
+        h[3 + c] = h1;
     }
+}
+
+// o_rq = sum_i x[i][r] conj(y[i][q]) over the two spin rows
+__device__ __forceinline__ void outer_half(const cx<double> (&x)[6], const cx<double> (&y)[6],
+                                           double (&o)[18]) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            double re = 0, im = 0;
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const cx<double> u = x[3 * i + r], v = y[3 * i + q];
+                re = fma(u.re, v.re, fma(u.im, v.im, re));
+                im = fma(u.im, v.re, fma(-u.re, v.im, im));
+            }
+            o[2 * (3 * r + q)] = re;
+            o[2 * (3 * r + q) + 1] = im;
+        }
 }
 
 struct ForceArgs {
@@ -71,94 +88,170 @@ struct ForceArgs {
     double2* grad;  // [4][lex][3][3] or null
 };
 
-__global__ void force_kernel(ForceArgs a) {
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= 8 * a.Vh) return;
-    const int mu = (int)(i % 4);
-    const long site = i / 4;
-    const int par = (int)(site / a.Vh);
-    const long cb = site - par * a.Vh;
+constexpr int FPS = 19;  // LDS row of one lane's partial: 9 complex + 1 pad
+
+// site index (both parities: par * Vh + cb) -> parity, cb and coordinates
+__device__ __forceinline__ void site_at(const ForceArgs& a, long site, int& par, long& cb,
+                                        int c[4]) {
     Box lat;
     for (int m = 0; m < 4; ++m) {
         lat.E[m] = a.L[m];
         lat.off[m] = 0;
     }
     lat.Vh = a.Vh;
-    int c[4];
+    par = (int)(site / a.Vh);
+    cb = site - par * a.Vh;
     box_coords(lat, cb, par, c);
+}
+
+__device__ __forceinline__ long forward_cb(const ForceArgs& a, const int c[4], int mu) {
+    Box lat;
+    for (int m = 0; m < 4; ++m) {
+        lat.E[m] = a.L[m];
+        lat.off[m] = 0;
+    }
+    lat.Vh = a.Vh;
     int n[4] = {c[0], c[1], c[2], c[3]};
-    n[mu] = (n[mu] + 1) % a.L[mu];
-    const long ncb = box_cb(lat, n);
-    const int npar = 1 - par;
-    cx<double> P[9], Q[9];
-    for (int k = 0; k < 9; ++k) P[k] = Q[k] = {0, 0};
-    for (int s = 0; s < a.Ls; ++s) {
-        cx<double> ax[12], bx[12], by[12], ay[12], pb[12], pa[12];
-        load_spinor<F64>(a.a[par], cb * a.Ls + s, ax);
-        load_spinor<F64>(a.b[par], cb * a.Ls + s, bx);
-        load_spinor<F64>(a.b[npar], ncb * a.Ls + s, by);
-        load_spinor<F64>(a.a[npar], ncb * a.Ls + s, ay);
-        proj_full<-1>(mu, by, pb);  // (1 - g) b(x+mu)
-        proj_full<+1>(mu, ay, pa);  // (1 + g) a(x+mu)
-        for (int sp = 0; sp < 4; ++sp)
-            for (int r = 0; r < 3; ++r)
-                for (int q = 0; q < 3; ++q) {
-                    // P_rq += pb_r conj(ax_q) ; Q_rq += bx_r conj(pa_q)
-                    const cx<double> x1 = pb[sp * 3 + r], y1 = ax[sp * 3 + q];
-                    P[r * 3 + q].re += x1.re * y1.re + x1.im * y1.im;
-                    P[r * 3 + q].im += x1.im * y1.re - x1.re * y1.im;
-                    const cx<double> x2 = bx[sp * 3 + r], y2 = pa[sp * 3 + q];
-                    Q[r * 3 + q].re += x2.re * y2.re + x2.im * y2.im;
-                    Q[r * 3 + q].im += x2.im * y2.re - x2.re * y2.im;
-                }
-    }
-    // eta U_mu(x): forward link of this site (sign folded in)
-    cx<double> U[9];
-    for (int k = 0; k < 9; ++k) {
-        const double2 t = a.links[(((long)par * a.Vh + cb) * 8 + mu) * 9 + k];
-        U[k] = {t.x, t.y};
-    }
-    const long lex = (((long)c[3] * a.L[2] + c[2]) * a.L[1] + c[1]) * a.L[0] + c[0];
+    n[mu] = n[mu] + 1 == a.L[mu] ? 0 : n[mu] + 1;
+    return box_cb(lat, n);
+}
+
+// value of the neighbouring lane (lane ^ 1): DPP quad_perm [1,0,3,2] on both
+// halves of the double
+__device__ __forceinline__ double swap_pair(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0xB1, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// workgroup -> range of sites: the hardware deals workgroups to the eight
+// XCDs in turn, so workgroup b is given position (b mod 8) * G/8 + b/8 (with
+// the remainder spread over the first XCDs); each XCD then walks one
+// contiguous range of sites and finds most neighbours in its own L2
+__device__ __forceinline__ long xcd_block() {
+    const unsigned G = gridDim.x, lid = blockIdx.x;
+    const unsigned q = G >> 3, r = G & 7, k = lid & 7;
+    return (long)(k * q + (k < r ? k : r) + (lid >> 3));
+}
+
+// one lane per (site, entry (r, q)) of direction mu: F and the gradient
+__device__ __forceinline__ void force_out(const ForceArgs& a, long st, int mu, int e,
+                                          const double2* P, const double2* Q) {
+    int p2, c2[4];
+    long cb2;
+    site_at(a, st, p2, cb2, c2);
     const long V4 = 2 * a.Vh;
+    const long lex = (((long)c2[3] * a.L[2] + c2[2]) * a.L[1] + c2[1]) * a.L[0] + c2[0];
+    const int r = e / 3, q = e - 3 * (e / 3);
+    const double2* U = a.links + st * 72 + 9 * mu;  // eta U_mu(x)
     if (a.F) {
-        // G = (eta U) P - Q (eta U)^+ = eta (U P - Q U^+)
-        cx<double> G[9];
-        for (int r = 0; r < 3; ++r)
-            for (int q = 0; q < 3; ++q) {
-                cx<double> g = {0, 0};
-                for (int k = 0; k < 3; ++k) {
-                    cfma(g, U[r * 3 + k], P[k * 3 + q]);
-                    const cx<double> uc = {U[q * 3 + k].re, -U[q * 3 + k].im};  // (U^+)_{kq}
-                    const cx<double> t = cmul(Q[r * 3 + k], uc);
-                    g.re -= t.re;
-                    g.im -= t.im;
+        // G = (eta U) P - Q (eta U)^+ at (r, q) and (q, r); F = TA[(G - G^+)/(2i)]
+        cx<double> g[2];
+#pragma unroll
+        for (int z = 0; z < 2; ++z) {
+            const int rr = z ? q : r, qq = z ? r : q;
+            cx<double> acc = {0, 0};
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double2 u1 = U[3 * rr + j], p1 = P[3 * j + qq];
+                const double2 q1 = Q[3 * rr + j], u2 = U[3 * qq + j];
+                acc.re += u1.x * p1.x - u1.y * p1.y - (q1.x * u2.x + q1.y * u2.y);
+                acc.im += u1.x * p1.y + u1.y * p1.x - (q1.y * u2.x - q1.x * u2.y);
+            }
+            g[z] = acc;
+        }
+        cx<double> f = {0.5 * (g[0].im + g[1].im), -0.5 * (g[0].re - g[1].re)};
+        if (r == q) {
+            // trace of (G - G^+)/(2i) = sum_d Im G_dd
+            double tr = 0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const double2 u1 = U[3 * d + j], p1 = P[3 * j + d];
+                    const double2 q1 = Q[3 * d + j];
+                    tr += u1.x * p1.y + u1.y * p1.x - (q1.y * u1.x - q1.x * u1.y);
                 }
-                G[r * 3 + q] = g;
-            }
-        cx<double> Fm[9];
-        double tr = 0;
-        for (int r = 0; r < 3; ++r)
-            for (int q = 0; q < 3; ++q) {
-                // (G - G^+)/(2i) : (x - conj(y)) / (2i) with x = G_rq, y = G_qr
-                const cx<double> x = G[r * 3 + q], y = G[q * 3 + r];
-                const double dre = x.re - y.re, dim = x.im + y.im;
-                Fm[r * 3 + q] = {0.5 * dim, -0.5 * dre};
-                if (r == q) tr += Fm[r * 3 + q].re;
-            }
-        for (int r = 0; r < 3; ++r) Fm[r * 4].re -= tr / 3.0;
-        double2* out = a.F + ((long)mu * V4 + lex) * 9;
-        for (int k = 0; k < 9; ++k) out[k] = make_double2(Fm[k].re, Fm[k].im);
+            f.re -= tr / 3.0;
+        }
+        a.F[((long)mu * V4 + lex) * 9 + e] = make_double2(f.re, f.im);
     }
     if (a.grad) {
         // g = -eta (P^+ + Q), eta = -1 only for the time link that wraps
-        const double eta = (mu == 3 && c[3] == a.L[3] - 1 && a.antiperiodic_t) ? -1.0 : 1.0;
-        double2* out = a.grad + ((long)mu * V4 + lex) * 9;
-        for (int r = 0; r < 3; ++r)
-            for (int q = 0; q < 3; ++q) {
-                const cx<double> pc = P[q * 3 + r];  // (P^+)_{rq} = conj(P_qr)
-                out[r * 3 + q] = make_double2(-eta * (pc.re + Q[r * 3 + q].re),
-                                              -eta * (-pc.im + Q[r * 3 + q].im));
+        const double eta = (mu == 3 && c2[3] == a.L[3] - 1 && a.antiperiodic_t) ? -1.0 : 1.0;
+        const double2 pc = P[3 * q + r];  // (P^+)_{rq} = conj(P_qr)
+        const double2 qv = Q[e];
+        a.grad[((long)mu * V4 + lex) * 9 + e] =
+            make_double2(-eta * (pc.x + qv.x), -eta * (-pc.y + qv.y));
+    }
+}
+
+constexpr int FORCE_THREADS = 64;  // one wave per workgroup: its barriers cost no waiting
+
+// 3 waves per SIMD (at most 168 VGPRs; the LDS of a workgroup allows 15)
+template <int LS>
+__global__ __launch_bounds__(FORCE_THREADS, 3) void force_kernel(ForceArgs a) {
+    // sites per workgroup, one lane per (site, s); Ls is even, so lanes s and
+    // s ^ 1 belong to the same site
+    constexpr int SPB = FORCE_THREADS / LS;
+    constexpr int R = LS / 2;  // partials per site after the pair sum
+    __shared__ double part[SPB * R][FPS];
+    __shared__ double2 sum[SPB][72];  // [P, Q][mu][3x3], summed over s
+    const int t = threadIdx.x;
+    const int sl = t / LS;
+    const int s = t - sl * LS;
+    const long site0 = xcd_block() * SPB;
+    const long nsite = 2 * a.Vh;
+    const bool act = sl < SPB && site0 + sl < nsite;
+    int par = 0, c[4] = {0, 0, 0, 0};
+    long cb = 0;
+    if (act) site_at(a, site0 + sl, par, cb, c);
+    // w = 0: P_mu = sum h-(b(x+mu)) h-(a(x))^+ ; w = 1: Q_mu = sum h+(b(x)) h+(a(x+mu))^+.
+    // The site's own spinor (a(x), then b(x)) stays in registers for the four
+    // directions; only the neighbour is loaded per direction.
+#pragma unroll 1
+    for (int w = 0; w < 2; ++w) {
+        cx<double> own[12];
+        if (act) load_spinor_at<F64>(w == 0 ? a.a[par] : a.b[par], cb * LS, s, LS, own);
+#pragma unroll 1
+        for (int mu = 0; mu < 4; ++mu) {
+            if (act) {
+                const long ncb = forward_cb(a, c, mu);
+                cx<double> nb[12], hu[6], hv[6];
+                load_spinor_at<F64>(w == 0 ? a.b[1 - par] : a.a[1 - par], ncb * LS, s, LS, nb);
+                if (w == 0) {
+                    proj_half<-1>(mu, nb, hu);
+                    proj_half<-1>(mu, own, hv);
+                } else {
+                    proj_half<+1>(mu, own, hu);
+                    proj_half<+1>(mu, nb, hv);
+                }
+                double o[18];
+                outer_half(hu, hv, o);
+#pragma unroll
+                for (int k = 0; k < 18; ++k) o[k] += swap_pair(o[k]);  // slices s and s ^ 1
+                if (!(s & 1))
+#pragma unroll
+                    for (int k = 0; k < 18; ++k) part[t >> 1][k] = o[k];
             }
+            __syncthreads();
+            for (int k = t; k < SPB * 9; k += FORCE_THREADS) {
+                const int q = k / 9, e = k - 9 * q;
+                double re = 0, im = 0;
+                if (site0 + q < nsite)
+                    for (int j = 0; j < R; ++j) {
+                        re += part[q * R + j][2 * e];
+                        im += part[q * R + j][2 * e + 1];
+                    }
+                sum[q][(4 * w + mu) * 9 + e] = make_double2(re, im);
+            }
+            __syncthreads();
+        }
+    }
+    for (int k = t; k < SPB * 36; k += FORCE_THREADS) {
+        const int q = k / 36, mu = (k - 36 * q) / 9, e = k - 36 * q - 9 * mu;
+        if (site0 + q < nsite) force_out(a, site0 + q, mu, e, sum[q] + 9 * mu, sum[q] + 36 + 9 * mu);
     }
 }
 
@@ -203,8 +296,19 @@ extern "C" int mspcg_force(mspcg_ctx* c, const void* X_dev, const void* Y_dev, v
     a.antiperiodic_t = c->act.antiperiodic_t;
     a.F = (double2*)F_dev;
     a.grad = (double2*)G_dev;
-    const long n = 8 * c->Vh;
-    hipLaunchKernelGGL(force_kernel, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, a);
+    const long nsites = 2 * c->Vh;
+    switch (c->Ls) {
+#define MSPCG_CASE(L)                                                                      \
+    case L: {                                                                              \
+        constexpr int spb = FORCE_THREADS / L;                                             \
+        hipLaunchKernelGGL(force_kernel<L>, dim3((unsigned)((nsites + spb - 1) / spb)),     \
+                           dim3(FORCE_THREADS), 0, st, a);                                 \
+        break;                                                                             \
+    }
+        MSPCG_LS_LIST(MSPCG_CASE)
+#undef MSPCG_CASE
+        default: return MSPCG_EUNSUPPORTED;
+    }
     if (hipGetLastError() != hipSuccess) return MSPCG_EHIP;
     MSPCG_HIP(hipStreamSynchronize(st));
     return MSPCG_OK;
