@@ -149,10 +149,10 @@ typedef struct {
     int rhs_normal;       /* 1: b is an even field solved directly as A x = b (x: even
                              field, odd sites zero); 0: solve D x = b */
     int batch_kernels;    /* mspcg_solve_batch with MSPCG: 0 = each block-hop stage of the
-                             local solves runs for every lattice in one persistent launch over
-                             a (lattice, block, tile) work list that skips converged lattices
-                             (when every lattice's Ls is 8, 12 or 16 and there are at most 8);
-                             1 = one launch per lattice and stage */
+                             local solves runs as one persistent launch per Ls over a
+                             (lattice, block, workgroup) work list that skips converged
+                             lattices (when every lattice's Ls is 8, 12 or 16); 1 = one launch
+                             per lattice and stage */
 } mspcg_solve_params;
 
 /* Launch tuning.  Hop kernels visit their output sites in 4D tiles so that

@@ -6,7 +6,7 @@ namespace mspcg {
 
 template int launch_hop<F32>(const HopArgs<F32>&, int, int, bool, hipStream_t);
 template long hop_grid_x<F32>(long, int);
-template int launch_multi_hop<F32>(const MultiHop<F32>*, long, bool, bool, bool, bool,
-                                    hipStream_t);
+template int launch_multi_hop<F32>(const MultiHop<F32>*, long, int, bool, bool, bool,
+                                    bool, hipStream_t);
 
 }  // namespace mspcg

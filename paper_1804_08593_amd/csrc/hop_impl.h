@@ -39,6 +39,17 @@
 #ifndef MSPCG_HOP_PF16
 #define MSPCG_HOP_PF16 1
 #endif
+// MSPCG_HOP_MFMA: FP16-storage hops at Ls = 16 multiply links by spinors on
+// the matrix cores (see hop_body).  Off by default: the hop is bound by HBM
+// and LDS traffic, not by its 1320 flops per 5D site, and the operand staging
+// the matrix-core form needs made the 12^3x24 domain hop 11% slower (463 us
+// against 416 us) on MI355X.  Build with -DMSPCG_HOP_MFMA=1 to select it.
+#ifndef MSPCG_HOP_MFMA
+#define MSPCG_HOP_MFMA 0
+#endif
+#ifndef MSPCG_HOP_MFMA_WAVES
+#define MSPCG_HOP_MFMA_WAVES 4
+#endif
 
 namespace mspcg {
 
@@ -251,7 +262,9 @@ __device__ __forceinline__ void sfor(F&& f) {
 // arithmetic, not memory, sets the pace)
 template <class S, int LS, bool EPA, bool CG>
 constexpr int hop_min_waves() {
-    return (S::has_scale && !EPA && !CG && (LS == 8 || LS == 16)) ? 6 : MSPCG_HOP_MINWAVES;
+    // the matrix-core variant (FP16, Ls = 16) fits 128 VGPRs
+    if (S::has_scale && LS == 16 && MSPCG_HOP_MFMA) return MSPCG_HOP_MFMA_WAVES;
+    return (S::has_scale && !EPA && !CG && LS == 8) ? 6 : MSPCG_HOP_MINWAVES;
 }
 
 // LDS layout of one hop workgroup (SPB sites x LS lanes).
@@ -272,9 +285,56 @@ struct HopShape {
     // the s-exchange array serves both the chain programs (EPH/EPA) and the
     // single-step programs applied by neighbour exchange
     static constexpr int EPI_BYTES = SPB * 12 * LSP * (int)sizeof(cx<T>);
-    static constexpr int LNK_BYTES = LDSL ? SPB * LSTR * 16 : 16;
+    // FP16 storage at Ls = 16 (a wave = 4 sites x 16 s): the SU(3) products
+    // run as v_mfma_f32_16x16x32_f16 with the links staged in LDS as operand
+    // rows (1 KB per site) and a 16-byte zero row
+    static constexpr bool MF = S::has_scale && LS == 16 && MSPCG_HOP_MFMA;
+    static constexpr int MF_SITE = 1024;
+    static constexpr int LNK_BYTES = MF ? SPB * MF_SITE + 16 : (LDSL ? SPB * LSTR * 16 : 16);
     static constexpr int LDS_BYTES = EPI_BYTES > LNK_BYTES ? EPI_BYTES : LNK_BYTES;
 };
+
+typedef _Float16 mf_half8 __attribute__((ext_vector_type(8)));
+typedef float mf_float4 __attribute__((ext_vector_type(4)));
+
+// One 16-byte operand row of the matrix-core link product: for link row i
+// (entries u_i0..u_i2), op 0 gives [Re u, 0, -Im u, 0] and op 1 [Im u, 0, Re u, 0],
+// so that with a spinor colour vector packed as [Re psi, 0, Im psi, 0] the
+// products give Re(U psi)_i and Im(U psi)_i (FP16 inputs, exact products,
+// FP32 accumulation).
+__device__ __forceinline__ nt_u4 mf_link_row(const unsigned (&e)[3], int op) {
+    // e[j]: __half2 (Re, Im) of u_ij as a 32-bit word
+    const unsigned re01 = (e[0] & 0xffffu) | (e[1] << 16);
+    const unsigned im01 = (e[0] >> 16) | (e[1] & 0xffff0000u);
+    const unsigned re2 = e[2] & 0xffffu, im2 = e[2] >> 16;
+    if (op == 0)  // [Re u0, Re u1, Re u2, 0, -Im u0, -Im u1, -Im u2, 0]
+        return nt_u4{re01, re2, im01 ^ 0x80008000u, im2 ^ 0x8000u};
+    return nt_u4{im01, im2, re01, re2};
+}
+
+// Spin component sp of a raw FP16 spinor (unscaled) packed as an MFMA B
+// operand: [Re c0, Re c1, Re c2, 0, Im c0, Im c1, Im c2, 0] for the colours
+// of that spin.
+__device__ __forceinline__ mf_half8 mf_spin_operand(const RawSpinor<F16>& r, int sp) {
+    unsigned w[12];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        w[4 * k + 0] = r.c[k].x;
+        w[4 * k + 1] = r.c[k].y;
+        w[4 * k + 2] = r.c[k].z;
+        w[4 * k + 3] = r.c[k].w;
+    }
+    const unsigned w0 = w[3 * sp], w1 = w[3 * sp + 1], w2 = w[3 * sp + 2];
+    // byte selects: low halves of w0, w1 (the real parts), high halves (imaginary)
+    const nt_u4 v{__builtin_amdgcn_perm(w1, w0, 0x05040100u), w2 & 0xffffu,
+                  __builtin_amdgcn_perm(w1, w0, 0x07060302u), w2 >> 16};
+    return __builtin_bit_cast(mf_half8, v);
+}
+
+template <int LS>
+constexpr int SPB_THREADS() {
+    return (256 / LS) * LS;
+}
 
 // One workgroup's share of a hop launch: output sites [bx*SPB, (bx+1)*SPB)
 // of domain d (in traversal order); gx = workgroups per domain (indexes the
@@ -340,7 +400,21 @@ __device__ __forceinline__ void hop_body(const HopArgs<S>& a, int bx, int d, int
         for (int m = 0; m < 4; ++m) lc[m] = gc[m] - g.link.off[m];
         gl = a.links + (long)d * a.link_dom_stride +
              ((long)g.out_par * g.link.Vh + box_cb(g.link, lc)) * 72;
-        if constexpr (LDSL) {
+        if constexpr (SH::MF) {
+            // 64 operand rows per site (direction, op, row i), i = 3 zero
+            const unsigned* src = reinterpret_cast<const unsigned*>(gl);
+            for (int r = s; r < 64; r += LS) {
+                const int dir = r >> 3, op = (r >> 2) & 1, i = r & 3;
+                nt_u4 v{0u, 0u, 0u, 0u};
+                if (i < 3) {
+                    unsigned e[3];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) e[j] = src[dir * 9 + i * 3 + j];
+                    v = mf_link_row(e, op);
+                }
+                *reinterpret_cast<nt_u4*>(smem + sl * SH::MF_SITE + r * 16) = v;
+            }
+        } else if constexpr (LDSL) {
             const nt_u4* src = reinterpret_cast<const nt_u4*>(gl);
             for (int j = s; j < NCH; j += LS) {
                 nt_u4 v;
@@ -360,13 +434,89 @@ __device__ __forceinline__ void hop_body(const HopArgs<S>& a, int bx, int d, int
             }
         }
     }
-    if constexpr (LDSL) __syncthreads();
+    if constexpr (SH::MF) {
+        // sites without output (beyond the box or list) get zero operand rows,
+        // so no stale LDS value enters a matrix product
+        if (!active && sl < SPB)
+            for (int r = s; r < 64; r += LS)
+                *reinterpret_cast<nt_u4*>(smem + sl * SH::MF_SITE + r * 16) = nt_u4{0u, 0u, 0u, 0u};
+        if (threadIdx.x == 0)
+            *reinterpret_cast<nt_u4*>(smem + SPB * SH::MF_SITE) = nt_u4{0u, 0u, 0u, 0u};
+        __syncthreads();
+    } else if constexpr (LDSL) {
+        __syncthreads();
+    }
 
     constexpr int KC = Chunk<S>::K;
     cx<T> acc[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
-    if (active) {
+    if constexpr (SH::MF) {
+        // Every lane of the wave takes part in the matrix products (lanes
+        // without an output or a neighbour use zero operands).  The wave's 4
+        // sites x 16 s are the 16 columns (s) and the 4 blocks of 4 rows
+        // (site, colour row i) of a 16x16x32 product whose A operand is
+        // block-diagonal: lane L holds row L%16 = (site gm, row im) against
+        // the K block L/16 = site gk, nonzero only when gm == gk.
+        const long ibase = (long)d * g.in.Vh;
+        const InPos ip = in_position(g, gc);
+        gchar* in_d = uniform_ptr(reinterpret_cast<const char*>(a.in.data) + ibase * LS * KC * 16);
+        gchar* sc_d = uniform_ptr(reinterpret_cast<const char*>(a.in.scale + ibase * LS));
+        const unsigned s16 = (unsigned)s * 16u, s4 = (unsigned)s * 4u;
+        const int L = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+        const int gm = (L & 15) >> 2, im = L & 3, gk = L >> 4;
+        const unsigned char* arow = (gm == gk) ? smem + (4 * wv + gm) * SH::MF_SITE + im * 16
+                                               : smem + SPB * SH::MF_SITE;
+        const int astep = (gm == gk) ? 64 : 0;  // bytes between the op-row groups of a direction
+        constexpr int SF = DAG ? 1 : -1;
+        constexpr int SB = -SF;
+        sfor<8>([&](auto di) {
+            constexpr int D = decltype(di)::value;
+            constexpr int MU = D / 2;
+            constexpr bool FWD = (D % 2) == 0;
+            long n = 0;
+            const bool ok = active && neighbour<MU, FWD ? 1 : 0>(g, ip, n);
+            // a dropped hop (or a lane without output) reads the box's first
+            // site, finite data, and weighs it by zero: no branch around the
+            // loads, and no undefined value enters the matrix product
+            const unsigned un = ok ? (unsigned)n : 0u;
+            RawSpinor<S> raw;
+            gchar* pb = in_d + (unsigned long)((unsigned)__umul24(un, LS * KC * 16) + s16);
+#pragma unroll
+            for (int k = 0; k < KC; ++k)
+                raw.c[k] = *reinterpret_cast<const __attribute__((address_space(1))) nt_u4*>(
+                    pb + k * LS * 16);
+            const float scn = *reinterpret_cast<const __attribute__((address_space(1))) float*>(
+                sc_d + (unsigned long)((unsigned)__umul24(un, LS * 4) + s4));
+            raw.sc = ok ? scn : 0.f;
+            constexpr int LDIR = FWD ? MU : 4 + MU;  // link slot of this direction
+            const mf_half8 are =
+                *reinterpret_cast<const mf_half8*>(arow + astep * (2 * LDIR));
+            const mf_half8 aim =
+                *reinterpret_cast<const mf_half8*>(arow + astep * (2 * LDIR + 1));
+            cx<float> up[12];
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp) {
+                const mf_half8 b = mf_spin_operand(raw, sp);
+                const mf_float4 z = {0.f, 0.f, 0.f, 0.f};
+                const mf_float4 dr = __builtin_amdgcn_mfma_f32_16x16x32_f16(are, b, z, 0, 0, 0);
+                const mf_float4 dm = __builtin_amdgcn_mfma_f32_16x16x32_f16(aim, b, z, 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) up[sp * 3 + i] = {dr[i], dm[i]};
+            }
+            // (1 + sig g_mu) U psi = U (1 + sig g_mu) psi: project the products
+            cx<float> h[6];
+            project<MU, FWD ? SF : SB, false>(up, h, 1.f);
+            reconstruct<MU, FWD ? SF : SB>(h, acc, raw.sc);
+            // finish this direction here: the empty asm pins the accumulators
+            // (so the products are not kept live and folded in at the end)
+            // and the scheduling barrier keeps the next direction's loads
+            // below; both cost less than the registers they save
+#pragma unroll
+            for (int c = 0; c < 12; ++c) asm volatile("" : "+v"(acc[c].re), "+v"(acc[c].im));
+            __builtin_amdgcn_sched_barrier(0);
+        });
+    } else if (active) {
         const long ibase = (long)d * g.in.Vh;
         const InPos ip = in_position(g, gc);
         // the domain's input box (a workgroup-uniform base, kept in scalar
@@ -669,17 +819,12 @@ long hop_grid_x(long Vh, int Ls) {
     return (Vh + spb - 1) / spb;
 }
 
-template <class S>
-constexpr int multi_lds_bytes() {
-    constexpr int a = HopShape<S, 8>::LDS_BYTES, b = HopShape<S, 12>::LDS_BYTES,
-                  c = HopShape<S, 16>::LDS_BYTES;
-    return a > b ? (a > c ? a : c) : (b > c ? b : c);
-}
-
-template <class S, bool DAG, bool EPH, bool EPA, bool CG>
-__global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void multi_hop_kernel(
+// One launch over a work list of several lattices that share Ls (launch
+// bounds and LDS as for one lattice's hop).
+template <class S, int LS, bool DAG, bool EPH, bool EPA, bool CG>
+__global__ __launch_bounds__(256, (hop_min_waves<S, LS, EPA, CG>())) void multi_hop_kernel(
     const MultiHop<S>* __restrict__ m) {
-    __shared__ __attribute__((aligned(16))) unsigned char smem[multi_lds_bytes<S>()];
+    __shared__ __attribute__((aligned(16))) unsigned char smem[HopShape<S, LS>::LDS_BYTES];
     const int n = m->n;
     const long items = m->first[n];
     for (long it = blockIdx.x; it < items; it += gridDim.x) {
@@ -690,23 +835,17 @@ __global__ __launch_bounds__(256, MSPCG_HOP_MINWAVES) void multi_hop_kernel(
         const int gx = m->gx[i];
         const long r = it - m->first[i];
         const int d = (int)(r / gx), bx = (int)(r - (long)d * gx);
-        switch (m->ls[i]) {
-            case 8: hop_body<S, 8, DAG, EPH, EPA, CG>(a, bx, d, gx, smem); break;
-            case 12: hop_body<S, 12, DAG, EPH, EPA, CG>(a, bx, d, gx, smem); break;
-            default: hop_body<S, 16, DAG, EPH, EPA, CG>(a, bx, d, gx, smem); break;
-        }
+        hop_body<S, LS, DAG, EPH, EPA, CG>(a, bx, d, gx, smem);
         __syncthreads();  // LDS is reused by the next item
     }
 }
 
-template <class S>
-int launch_multi_hop(const MultiHop<S>* dev, long items, bool dag, bool eph, bool epa, bool cg,
-                     hipStream_t st) {
-    if (items <= 0) return 0;
-    // persistent grid: at most 4 workgroups per CU, each walking the list
-    const long g = items < 1024 ? items : 1024;
-    dim3 grid((unsigned)g), block(256);
-#define MSPCG_MH(D, H, A, C) hipLaunchKernelGGL((multi_hop_kernel<S, D, H, A, C>), grid, block, 0, st, dev)
+template <class S, int LS>
+static int launch_multi_ls(const MultiHop<S>* dev, dim3 grid, bool dag, bool eph, bool epa,
+                           bool cg, hipStream_t st) {
+    dim3 block(SPB_THREADS<LS>());
+#define MSPCG_MH(D, H, A, C) \
+    hipLaunchKernelGGL((multi_hop_kernel<S, LS, D, H, A, C>), grid, block, 0, st, dev)
     if (!dag && eph && !epa && !cg) MSPCG_MH(false, true, false, false);
     else if (!dag && !eph && !epa && !cg) MSPCG_MH(false, false, false, false);
     else if (dag && eph && !epa && !cg) MSPCG_MH(true, true, false, false);
@@ -714,6 +853,23 @@ int launch_multi_hop(const MultiHop<S>* dev, long items, bool dag, bool eph, boo
     else if (dag && cg) MSPCG_MH(true, true, true, true);
     else return -1;
 #undef MSPCG_MH
+    return 0;
+}
+
+template <class S>
+int launch_multi_hop(const MultiHop<S>* dev, long items, int Ls, bool dag, bool eph, bool epa,
+                     bool cg, hipStream_t st) {
+    if (items <= 0) return 0;
+    // persistent grid: at most 4 workgroups per CU, each walking the list
+    dim3 grid((unsigned)(items < 1024 ? items : 1024));
+    int e;
+    switch (Ls) {
+        case 8: e = launch_multi_ls<S, 8>(dev, grid, dag, eph, epa, cg, st); break;
+        case 12: e = launch_multi_ls<S, 12>(dev, grid, dag, eph, epa, cg, st); break;
+        case 16: e = launch_multi_ls<S, 16>(dev, grid, dag, eph, epa, cg, st); break;
+        default: return -1;
+    }
+    if (e) return e;
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

@@ -62,8 +62,8 @@ int launch_hop(const HopArgs<S>& a, int Ls, int ndom, bool dag, hipStream_t st);
 // The work list is (lattice i, domain d, workgroup bx): lattice i owns items
 // [first[i], first[i+1]), ndom_i * gx[i] of them; a workgroup walks the list
 // with a stride of the grid size and skips the items of lattices whose
-// `done` flag (a[i].done) is set.  Every lattice's Ls must be one of
-// kMultiHopLs; all share the kernel variant (dagger, chain programs, fused
+// `done` flag (a[i].done) is set.  The lattices of one launch share Ls (8, 12
+// or 16, multi_hop_ls) and the kernel variant (dagger, chain programs, fused
 // update).  The descriptor lives in device memory so a captured graph
 // replays it.
 constexpr int kMaxBatch = 8;
@@ -77,8 +77,8 @@ struct MultiHop {
 };
 bool multi_hop_ls(int Ls);  // Ls handled by the multi-lattice kernel
 template <class S>
-int launch_multi_hop(const MultiHop<S>* dev, long items, bool dag, bool eph, bool epa, bool cg,
-                     hipStream_t st);
+int launch_multi_hop(const MultiHop<S>* dev, long items, int Ls, bool dag, bool eph, bool epa,
+                     bool cg, hipStream_t st);
 template <class S>
 long hop_grid_x(long Vh, int Ls);  // workgroups per domain for Vh output sites
 

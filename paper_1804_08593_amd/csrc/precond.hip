@@ -653,23 +653,32 @@ static int precond_core(mspcg_ctx* c, int l, CField<F64> r, Field<F64> z, const 
 }
 
 // Local solves of several lattices interleaved stage by stage; with `multi`
-// every block-hop stage of all lattices is one persistent multi-lattice
-// launch (MultiHop), otherwise one launch per lattice.
+// every block-hop stage runs as one persistent launch per group of lattices
+// that share Ls (MultiHop), otherwise one launch per lattice.
 template <class S>
 struct BatchPrecondImpl : BatchPrecond {
     std::vector<Local<S>> L;
     std::vector<const int*> done;
-    // stages 0..2 (hops u, y, v), then hop 3 for (first step, last step) =
-    // (0,0) (0,1) (1,0) (1,1): descriptors in device memory
-    MultiHop<S>* dev = nullptr;
-    long items[7] = {};
-    bool dag[7] = {}, eph[7] = {}, epa[7] = {}, cgf[7] = {};
+    // per group of lattices with one Ls: descriptors in device memory for
+    // hops 0..2 (u, y, v), then hop 3 for (first step, last step) =
+    // (0,0) (0,1) (1,0) (1,1); items < 0 marks a kind of step l does not have
+    struct Group {
+        int Ls = 0;
+        std::vector<int> members;
+        MultiHop<S>* dev = nullptr;
+        long items[7] = {};
+        bool dag[7] = {}, eph[7] = {}, epa[7] = {}, cgf[7] = {};
+    };
+    std::vector<Group> groups;
     ~BatchPrecondImpl() override {
-        if (dev) (void)hipFree(dev);
+        for (Group& g : groups)
+            if (g.dev) (void)hipFree(g.dev);
     }
-    static bool chain(const FiveDProg& P) { return !P.identity && !(P.nsteps == 1 && P.kind[0] == STEP_BIDI); }
-    int build(int l) {
-        const int n = (int)L.size();
+    static bool chain(const FiveDProg& P) {
+        return !P.identity && !(P.nsteps == 1 && P.kind[0] == STEP_BIDI);
+    }
+    int build_group(Group& G, int l) {
+        const int n = (int)G.members.size();
         std::vector<MultiHop<S>> h(7);
         for (int k = 0; k < 7; ++k) {
             memset(&h[k], 0, sizeof(MultiHop<S>));
@@ -680,47 +689,71 @@ struct BatchPrecondImpl : BatchPrecond {
                 const bool want_first = ((k - 3) >> 1) & 1, want_last = (k - 3) & 1;
                 it = want_first ? 0 : (want_last ? l - 1 : 1);
                 if (it >= l || (it == 0) != want_first || (it == l - 1) != want_last) {
-                    items[k] = -1;
+                    G.items[k] = -1;
                     continue;
                 }
             }
             long first = 0;
-            for (int i = 0; i < n; ++i) {
+            for (int j = 0; j < n; ++j) {
+                const int i = G.members[j];
                 double bytes;
                 bool dg;
                 const HopArgs<S> a = local_hop<S>(L[i], stage, it, l, done[i], bytes, dg);
                 const long nout = a.site_list ? a.n_list : a.g.out.Vh;
                 const bool e1 = chain(a.ph), e2 = a.has_aux && chain(a.pa);
-                if (i == 0) {
-                    dag[k] = dg;
-                    eph[k] = e1;
-                    epa[k] = e2;
-                    cgf[k] = a.cg_r.data != nullptr;
-                } else if (e1 != eph[k] || e2 != epa[k]) {
+                if (j == 0) {
+                    G.dag[k] = dg;
+                    G.eph[k] = e1;
+                    G.epa[k] = e2;
+                    G.cgf[k] = a.cg_r.data != nullptr;
+                } else if (e1 != G.eph[k] || e2 != G.epa[k]) {
                     return MSPCG_EUNSUPPORTED;  // lattices need different kernel variants
                 }
-                h[k].a[i] = a;
-                h[k].ls[i] = L[i].c->Ls;
-                h[k].gx[i] = (int)hop_grid_x<S>(nout, L[i].c->Ls);
-                h[k].first[i] = first;
-                first += (long)L[i].c->dom.ndom * h[k].gx[i];
+                h[k].a[j] = a;
+                h[k].ls[j] = G.Ls;
+                h[k].gx[j] = (int)hop_grid_x<S>(nout, G.Ls);
+                h[k].first[j] = first;
+                first += (long)L[i].c->dom.ndom * h[k].gx[j];
             }
             h[k].first[n] = first;
             h[k].n = n;
-            items[k] = first;
+            G.items[k] = first;
         }
-        if (hipMalloc(&dev, 7 * sizeof(MultiHop<S>)) != hipSuccess) return MSPCG_ENOMEM;
-        if (hipMemcpy(dev, h.data(), 7 * sizeof(MultiHop<S>), hipMemcpyHostToDevice) != hipSuccess)
+        if (hipMalloc(&G.dev, 7 * sizeof(MultiHop<S>)) != hipSuccess) return MSPCG_ENOMEM;
+        if (hipMemcpy(G.dev, h.data(), 7 * sizeof(MultiHop<S>), hipMemcpyHostToDevice) != hipSuccess)
             return MSPCG_EHIP;
+        return 0;
+    }
+    int build(int l) {
+        for (size_t i = 0; i < L.size(); ++i) {
+            const int Ls = L[i].c->Ls;
+            if (!multi_hop_ls(Ls)) return MSPCG_EUNSUPPORTED;
+            Group* g = nullptr;
+            for (Group& x : groups)
+                if (x.Ls == Ls && (int)x.members.size() < kMaxBatch) g = &x;
+            if (!g) {
+                groups.emplace_back();
+                g = &groups.back();
+                g->Ls = Ls;
+            }
+            g->members.push_back((int)i);
+        }
+        for (Group& g : groups) {
+            const int e = build_group(g, l);
+            if (e) return e;
+        }
         return 0;
     }
     int hop(int k, int it, int l, hipStream_t st) {
         if (multi) {
             const int j = k < 3 ? k : 3 + 2 * (it == 0) + (it == l - 1);
-            if (items[j] < 0) return MSPCG_EHIP;
-            return launch_multi_hop<S>(dev + j, items[j], dag[j], eph[j], epa[j], cgf[j], st)
-                       ? MSPCG_EHIP
-                       : 0;
+            for (const Group& G : groups) {
+                if (G.items[j] < 0) return MSPCG_EHIP;
+                if (launch_multi_hop<S>(G.dev + j, G.items[j], G.Ls, G.dag[j], G.eph[j], G.epa[j],
+                                        G.cgf[j], st))
+                    return MSPCG_EHIP;
+            }
+            return 0;
         }
         for (size_t i = 0; i < L.size(); ++i) {
             double bytes;
@@ -764,14 +797,10 @@ static int make_batch_impl(mspcg_ctx* const* cs, int n, int l, const int* const*
     int e;
     for (int i = 0; i < n; ++i)
         if ((e = local_init<S>(cs[i], b->L[i]))) return e;
-    if (multi) {
-        bool ok = n <= kMaxBatch && l > 0;
-        for (int i = 0; i < n && ok; ++i) ok = multi_hop_ls(cs[i]->Ls);
-        if (ok) {
-            e = b->build(l);
-            if (e && e != MSPCG_EUNSUPPORTED) return e;
-            b->multi = e == 0;
-        }
+    if (multi && l > 0) {
+        e = b->build(l);
+        if (e && e != MSPCG_EUNSUPPORTED) return e;
+        b->multi = e == 0;
     }
     out = std::move(b);
     return 0;
