@@ -65,3 +65,14 @@ def test_dense_split_block_from_schur_matrix():
     K = SP.dense_K(act, U, A, (2, 2, 2, 2), "split")
     Kop = SP.dense_even(act, lambda v: O.block_precond_op(act, U, v, (2, 2, 2, 2), "split"))
     assert np.allclose(K, Kop, atol=1e-13)
+
+
+def test_dense_dirichlet_block_from_full_matrix():
+    """The Dirichlet block built from the dense D equals the oracle's
+    Dirichlet block operator (two constructions)."""
+    act, U = _tiny()
+    A = SP.dense_A(act, U)
+    D = SP.dense_full(act, lambda v: O.dwf(act, U, v))
+    K = SP.dense_K(act, U, A, (2, 2, 2, 2), "dirichlet", D=D)
+    Kop = SP.dense_even(act, lambda v: O.block_precond_op(act, U, v, (2, 2, 2, 2), "dirichlet"))
+    assert np.allclose(K, Kop, atol=1e-13)
