@@ -827,7 +827,13 @@ __global__ __launch_bounds__(256, (hop_min_waves<S, LS, EPA, CG>())) void multi_
     __shared__ __attribute__((aligned(16))) unsigned char smem[HopShape<S, LS>::LDS_BYTES];
     const int n = m->n;
     const long items = m->first[n];
-    for (long it = blockIdx.x; it < items; it += gridDim.x) {
+    // the hardware deals workgroups to the eight XCDs in turn: the workgroups
+    // of XCD k walk the k-th contiguous eighth of the list, so that
+    // neighbouring tiles of one domain share an L2
+    const unsigned G = gridDim.x, k = blockIdx.x & 7;
+    const unsigned nk = (G >> 3) + (k < (G & 7) ? 1u : 0u);
+    const long lo = items * k / 8, hi = items * (k + 1) / 8;
+    for (long it = lo + (blockIdx.x >> 3); it < hi; it += nk) {
         int i = 0;
         while (i + 1 < n && it >= m->first[i + 1]) ++i;
         const HopArgs<S>& a = m->a[i];
@@ -840,12 +846,33 @@ __global__ __launch_bounds__(256, (hop_min_waves<S, LS, EPA, CG>())) void multi_
     }
 }
 
+// persistent grid: as many workgroups as the CUs hold at once (at least 8,
+// a multiple of 8 so that every XCD gets the same count), never more than
+// the items
+template <class S, int LS, bool D, bool H, bool A, bool C>
+static dim3 multi_grid(long items) {
+    static int resident = 0;  // per kernel instance; the library drives one device type
+    if (!resident) {
+        int dev = 0, cus = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, multi_hop_kernel<S, LS, D, H, A, C>,
+                                                         SPB_THREADS<LS>(), 0) != hipSuccess ||
+            cus <= 0 || per <= 0)
+            per = 4, cus = 256;
+        resident = ((cus * per + 7) / 8) * 8;
+    }
+    const long g = items < resident ? ((items + 7) / 8) * 8 : resident;
+    return dim3((unsigned)g);
+}
+
 template <class S, int LS>
-static int launch_multi_ls(const MultiHop<S>* dev, dim3 grid, bool dag, bool eph, bool epa,
+static int launch_multi_ls(const MultiHop<S>* dev, long items, bool dag, bool eph, bool epa,
                            bool cg, hipStream_t st) {
     dim3 block(SPB_THREADS<LS>());
-#define MSPCG_MH(D, H, A, C) \
-    hipLaunchKernelGGL((multi_hop_kernel<S, LS, D, H, A, C>), grid, block, 0, st, dev)
+#define MSPCG_MH(D, H, A, C)                                                                  \
+    hipLaunchKernelGGL((multi_hop_kernel<S, LS, D, H, A, C>), (multi_grid<S, LS, D, H, A, C>(items)), \
+                       block, 0, st, dev)
     if (!dag && eph && !epa && !cg) MSPCG_MH(false, true, false, false);
     else if (!dag && !eph && !epa && !cg) MSPCG_MH(false, false, false, false);
     else if (dag && eph && !epa && !cg) MSPCG_MH(true, true, false, false);
@@ -860,13 +887,11 @@ template <class S>
 int launch_multi_hop(const MultiHop<S>* dev, long items, int Ls, bool dag, bool eph, bool epa,
                      bool cg, hipStream_t st) {
     if (items <= 0) return 0;
-    // persistent grid: at most 4 workgroups per CU, each walking the list
-    dim3 grid((unsigned)(items < 1024 ? items : 1024));
     int e;
     switch (Ls) {
-        case 8: e = launch_multi_ls<S, 8>(dev, grid, dag, eph, epa, cg, st); break;
-        case 12: e = launch_multi_ls<S, 12>(dev, grid, dag, eph, epa, cg, st); break;
-        case 16: e = launch_multi_ls<S, 16>(dev, grid, dag, eph, epa, cg, st); break;
+        case 8: e = launch_multi_ls<S, 8>(dev, items, dag, eph, epa, cg, st); break;
+        case 12: e = launch_multi_ls<S, 12>(dev, items, dag, eph, epa, cg, st); break;
+        case 16: e = launch_multi_ls<S, 16>(dev, items, dag, eph, epa, cg, st); break;
         default: return -1;
     }
     if (e) return e;
