@@ -356,6 +356,30 @@ def sweep_readings(ctx, w, bd, x, args, log):
             log(f"[sweep] {name} l={l}: {st['outer_iters']} it {st['seconds']:.3f} s")
 
 
+def multisplit_compare(ctx, w, bd, x, args, log, sweeps=400):
+    """The multisplitting iteration itself (Sec. 2.1, eq. (2)) beside MSPCG
+    with the same local solves (literal blocks, l = 6, FP16): residual after
+    a number of sweeps and the contraction per sweep over the last 100."""
+    from paper_1804_08593_amd import mspcg
+
+    for blk in (tuple(w["block"]), tuple(w["dims"][:3]) + (w["dims"][3] // 2,)):
+        kw = dict(tol=args.tol, block=blk, pad=2, inner_iters=args.inner_iters,
+                  inner_prec=mspcg.FP16)
+        ms = ctx.solve(bd, x, mspcg.make_params(maxiter=20000, solver=mspcg.SOLVER_MSPCG, **kw))
+        st = ctx.solve(bd, x, mspcg.make_params(maxiter=sweeps, solver=mspcg.SOLVER_MULTISPLIT,
+                                                 **kw), history=sweeps, allow_noconv=True)
+        h = st["history"]
+        row = {"workload": args.workload, "block": list(blk), "l": args.inner_iters,
+               "mspcg_outer_iters": ms["outer_iters"], "mspcg_seconds": round(ms["seconds"], 4),
+               "multisplit_sweeps": st["outer_iters"], "multisplit_seconds": round(st["seconds"], 4),
+               "converged": st["converged"],
+               "resid_at": {str(k): float(h[k - 1]) for k in (1, 10, 50, 100, 200, 400)
+                            if k <= len(h)},
+               "rate_per_sweep": float((h[-1] / h[-101]) ** 0.01) if len(h) > 101 else None}
+        print(json.dumps(row), flush=True)
+        log(f"[multisplit] {blk}: {row}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -381,6 +405,8 @@ def main():
                     help="instead of the bench line: MSPCG with the workload's blocks for "
                          "every block reading (Dirichlet, pad 1, split Schur, literal) and "
                          "l = 2..8, one JSON line per solve")
+    ap.add_argument("--multisplit", action="store_true",
+                    help="multisplitting sweeps beside MSPCG on the workload, then exit")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-tuned-blocking", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-10)
@@ -435,6 +461,9 @@ def main():
 
     if args.sweep_readings:
         sweep_readings(ctx, w, bd, x, args, log)
+        return
+    if args.multisplit:
+        multisplit_compare(ctx, w, bd, x, args, log)
         return
 
     p_cg = mspcg.make_params(tol=args.tol, maxiter=20000, solver=mspcg.SOLVER_CG, timing=True)
