@@ -47,6 +47,15 @@
 #ifndef MSPCG_HOP_MFMA
 #define MSPCG_HOP_MFMA 0
 #endif
+// MSPCG_HOP_PK16: FP16-storage hops project and multiply by the link in
+// packed FP16 arithmetic (two halves per instruction, see dir_apply_pk) and
+// accumulate the directions in FP32.  It cuts the Ls = 16 block hop's VALU
+// instructions by a sixth (2007 -> 1670 in the kernel body) and its time by
+// 6% on MI355X (12^3x24 domains: 429 -> 403 us), with unchanged outer
+// iteration counts; -DMSPCG_HOP_PK16=0 keeps FP32 arithmetic throughout.
+#ifndef MSPCG_HOP_PK16
+#define MSPCG_HOP_PK16 1
+#endif
 #ifndef MSPCG_HOP_MFMA_WAVES
 #define MSPCG_HOP_MFMA_WAVES 4
 #endif
@@ -144,6 +153,62 @@ __device__ __forceinline__ void dir_apply(const cx<typename S::real> (&p)[12],
             cfma(t, u[i * 3 + 1], h[sp * 3 + 1]);
             cfma(t, u[i * 3 + 2], h[sp * 3 + 2]);
             w[sp * 3 + i] = t;
+        }
+    reconstruct<MU, SIG>(w, acc, k);
+}
+
+typedef _Float16 pk_h2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ pk_h2 pk_bits(unsigned v) { return __builtin_bit_cast(pk_h2, v); }
+__device__ __forceinline__ pk_h2 pk_bcast(_Float16 v) { return pk_h2{v, v}; }
+__device__ __forceinline__ pk_h2 pk_itimes(pk_h2 v) { return pk_h2{-v.y, v.x}; }  // i v
+template <int SIG>
+__device__ __forceinline__ pk_h2 pk_addsig(pk_h2 a, pk_h2 b) {  // a + SIG b
+    if constexpr (SIG > 0)
+        return a + b;
+    else
+        return a - b;
+}
+
+// acc += k (1 + SIG g_mu) U p on FP16 storage in packed FP16 arithmetic: p
+// (the stored neighbour, scaled to max |real| <= 1) and U (|U_ij| <= 1) stay
+// FP16, the projection is one packed add and each complex multiply-add two
+// packed FMAs per (Re, Im) pair; the products w = U h are widened to FP32 in
+// the reconstruct, where the neighbour's scale k multiplies them.
+template <int MU, int SIG>
+__device__ __forceinline__ void dir_apply_pk(const pk_h2 (&p)[12], const pk_h2 (&u)[9],
+                                             cx<float> (&acc)[12], float k) {
+    pk_h2 h[6];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const pk_h2 u0 = p[c], u1 = p[3 + c], d0 = p[6 + c], d1 = p[9 + c];
+        if constexpr (MU == 0) {  // e d = (-i d1, -i d0)
+            h[c] = pk_addsig<-SIG>(u0, pk_itimes(d1));
+            h[3 + c] = pk_addsig<-SIG>(u1, pk_itimes(d0));
+        } else if constexpr (MU == 1) {  // e d = (-d1, d0)
+            h[c] = pk_addsig<-SIG>(u0, d1);
+            h[3 + c] = pk_addsig<SIG>(u1, d0);
+        } else if constexpr (MU == 2) {  // e d = (-i d0, i d1)
+            h[c] = pk_addsig<-SIG>(u0, pk_itimes(d0));
+            h[3 + c] = pk_addsig<SIG>(u1, pk_itimes(d1));
+        } else {  // e d = d
+            h[c] = pk_addsig<SIG>(u0, d0);
+            h[3 + c] = pk_addsig<SIG>(u1, d1);
+        }
+    }
+    cx<float> w[6];
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            pk_h2 t = pk_bcast(u[i * 3].x) * h[sp * 3];
+            t = __builtin_elementwise_fma(pk_bcast(u[i * 3].y), pk_itimes(h[sp * 3]), t);
+#pragma unroll
+            for (int j = 1; j < 3; ++j) {
+                t = __builtin_elementwise_fma(pk_bcast(u[i * 3 + j].x), h[sp * 3 + j], t);
+                t = __builtin_elementwise_fma(pk_bcast(u[i * 3 + j].y), pk_itimes(h[sp * 3 + j]), t);
+            }
+            w[sp * 3 + i] = {(float)t.x, (float)t.y};
         }
     reconstruct<MU, SIG>(w, acc, k);
 }
@@ -277,8 +342,10 @@ struct HopShape {
     // entry (site, s, c) at (site * 12 + c) * LSP + s, so the lanes of a site
     // (consecutive s) and the chain threads (consecutive c) both hit distinct banks
     static constexpr int LSP = LS + 1;
-    // FP16 links are decoded to FP32 once, when staged; LE is the LDS entry
-    using LE = typename std::conditional<S::has_scale, nt_f2, E>::type;
+    // FP16 links are decoded to FP32 once, when staged (kept FP16 for the
+    // packed-FP16 products); LE is the LDS entry
+    static constexpr bool PK = S::has_scale && MSPCG_HOP_PK16 && !(LS == 16 && MSPCG_HOP_MFMA);
+    using LE = typename std::conditional<S::has_scale && !PK, nt_f2, E>::type;
     static constexpr int NCH = 72 * (int)sizeof(E) / 16;   // 16-byte chunks of one site's links
     static constexpr int LSTR = 72 * (int)sizeof(LE) / 16 + 1;  // padded LDS site stride (chunks)
     static constexpr bool LDSL = SPB * LSTR * 16 <= 40 * 1024;
@@ -422,7 +489,9 @@ __device__ __forceinline__ void hop_body(const HopArgs<S>& a, int bx, int d, int
                     v = __builtin_nontemporal_load(src + j);
                 else
                     v = src[j];
-                if constexpr (S::has_scale) {
+                if constexpr (SH::PK) {
+                    lnk[sl * LSTR + j] = v;
+                } else if constexpr (S::has_scale) {
                     const cx<float> e0 = h2f(v.x, 1.f), e1 = h2f(v.y, 1.f);
                     const cx<float> e2 = h2f(v.z, 1.f), e3 = h2f(v.w, 1.f);
                     nt_f4* dst = reinterpret_cast<nt_f4*>(lnk + sl * LSTR + 2 * j);
@@ -566,7 +635,23 @@ __device__ __forceinline__ void hop_body(const HopArgs<S>& a, int bx, int d, int
                 constexpr int MU = D / 2;
                 constexpr bool FWD = (D % 2) == 0;
                 constexpr int LD = (FWD ? MU : 4 + MU) * 9;  // first entry of this link
-                if (ok[j]) {
+                if constexpr (SH::PK) {
+                    static_assert(LDSL, "packed-FP16 hops read their links from LDS");
+                    if (ok[j]) {
+                        pk_h2 p[12], u[9];
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) {
+                            p[4 * q + 0] = pk_bits(raw[j].c[q].x);
+                            p[4 * q + 1] = pk_bits(raw[j].c[q].y);
+                            p[4 * q + 2] = pk_bits(raw[j].c[q].z);
+                            p[4 * q + 3] = pk_bits(raw[j].c[q].w);
+                        }
+                        const unsigned* le = reinterpret_cast<const unsigned*>(lnk + sl * LSTR) + LD;
+#pragma unroll
+                        for (int q = 0; q < 9; ++q) u[q] = pk_bits(le[q]);
+                        dir_apply_pk<MU, FWD ? SF : SB>(p, u, acc, raw[j].sc);
+                    }
+                } else if (ok[j]) {
                     cx<T> p[12];
                     decode_raw<S>(raw[j], p, false);
                     cx<T> u[9];

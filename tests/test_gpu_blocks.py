@@ -12,7 +12,7 @@ import torch
 
 import oracle as O
 from paper_1804_08593_amd import mspcg, synth
-from tests.gpu_util import dev, fp16_bar, host, relerr, say, setup, site_err
+from tests.gpu_util import cg16_bars, dev, host, k16_bars, relerr, say, setup, site_err
 
 pytestmark = pytest.mark.gpu
 
@@ -22,10 +22,8 @@ GEOMS = {
     "cut3": ((8, 8, 8, 8), 8, (4, 4, 4, 8)),   # 8 blocks, t spans the lattice
     "cut1": ((8, 8, 8, 8), 8, (8, 8, 8, 4)),   # 2 blocks, only t cut
 }
-# K = P_s Mhat_D^+ Mhat_D P_s stores p, B p, u, y, v and w once each in FP16,
-# and every hop reads FP16 links: 7 roundings on the chain
-KTOL = {mspcg.FP64: (1e-13, 1e-12), mspcg.FP32: (1e-5, 1e-4),
-        mspcg.FP16: (fp16_bar(7), 1e-2)}
+# FP16 bars: stored roundings plus the hops' FP16 arithmetic (gpu_util)
+KTOL = {mspcg.FP64: (1e-13, 1e-12), mspcg.FP32: (1e-5, 1e-4), mspcg.FP16: k16_bars()}
 
 
 def _ctx(name, seed=31):
@@ -87,10 +85,8 @@ def test_block_operator_geometry_ls16():
         assert err <= tol and serr <= stol
 
 
-# l local CG iterations: the start stores rho and p, every iteration stores
-# B p, u, y, v and the updated rho (and z at the end): 2 + 5 l roundings
 ITOL = {mspcg.FP64: lambda l: (1e-11, 1e-10), mspcg.FP32: lambda l: (1e-4, 1e-3),
-        mspcg.FP16: lambda l: (fp16_bar(2 + 5 * l), 5e-2)}
+        mspcg.FP16: cg16_bars}
 
 
 @pytest.mark.parametrize("prec", [mspcg.FP64, mspcg.FP32, mspcg.FP16])

@@ -8,7 +8,7 @@ import torch
 
 import oracle as O
 from paper_1804_08593_amd import mspcg, synth
-from tests.gpu_util import dev, fp16_bar, host, relerr, say, setup, site_err
+from tests.gpu_util import cg16_bars, dev, host, relerr, say, setup, site_err
 
 pytestmark = pytest.mark.gpu
 
@@ -45,8 +45,8 @@ def test_multisplitting_sweeps_match_oracle(sweeps, prec):
     if prec == mspcg.FP64:
         assert err <= 1e-11 and serr <= 1e-10 and herr <= 1e-10
     else:
-        # every sweep repeats the l-step local solve's 2 + 5 l FP16 roundings
-        bar = sweeps * fp16_bar(2 + 5 * 8)
+        # every sweep repeats the l-step local solve's FP16 roundings
+        bar = sweeps * cg16_bars(8)[0]
         assert err <= bar and herr <= bar
 
 
