@@ -85,6 +85,23 @@ def test_block_operator_geometry_ls16():
         assert err <= tol and serr <= stol
 
 
+def test_block_operator_geometry_ls12():
+    """Ls = 12 (the 16^3x32 and 32^3x64 workloads) with 4^4 blocks on 8^4."""
+    dims, Ls, blk = (8, 8, 8, 8), 12, (4, 4, 4, 4)
+    act, U, ctx = setup(dims, Ls, 1.8, 0.01, 1.5, 0.5, eps=0.2, gseed=37)
+    psi = O.parity_mask(act, synth.fermion_field(dims, Ls, 38), 0)
+    ref = O.block_precond_op(act, U, psi, blk, "literal")
+    for prec in (mspcg.FP64, mspcg.FP32, mspcg.FP16):
+        ctx.set_blocking(blk, 2)
+        out = torch.zeros(ctx.fshape, dtype=torch.complex128, device="cuda")
+        ctx.apply(mspcg.OP_KBLOCK, dev(psi), out, prec=prec)
+        got = host(out)
+        err, serr = relerr(got, ref), site_err(got, ref)
+        say(f"Ls12 K prec={prec}: relerr {err:.3e} max entry err {serr:.3e}")
+        tol, stol = KTOL[prec]
+        assert err <= tol and serr <= stol
+
+
 ITOL = {mspcg.FP64: lambda l: (1e-11, 1e-10), mspcg.FP32: lambda l: (1e-4, 1e-3),
         mspcg.FP16: cg16_bars}
 
