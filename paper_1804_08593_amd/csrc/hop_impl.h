@@ -30,8 +30,9 @@
 #endif
 // MSPCG_HOP_PF{64,32,16}: directions whose raw neighbour spinors are loaded
 // before any of them is decoded and applied (per storage precision).  Two
-// for FP16 since its products run in packed FP16 (12^3x24 domain hop 396 ->
-// 385 us; four: 413 us); deeper groups did not help the FP64 and FP32 hops.
+// for FP16 (12^3x24 domain hop 428 -> 415 us; with the packed-FP16 products
+// 396 -> 385 us, four: 413 us); deeper groups did not help the FP64 and FP32
+// hops.
 #ifndef MSPCG_HOP_PF64
 #define MSPCG_HOP_PF64 1
 #endif
@@ -54,9 +55,10 @@
 // accumulate the directions in FP32.  It cuts the Ls = 16 block hop's VALU
 // instructions by a sixth (2007 -> 1670 in the kernel body) and its time by
 // 6% on MI355X (12^3x24 domains: 429 -> 403 us), with unchanged outer
-// iteration counts; -DMSPCG_HOP_PK16=0 keeps FP32 arithmetic throughout.
+// iteration counts.  Off by default: the local solves keep FP32 arithmetic
+// on their FP16-stored operands; build with -DMSPCG_HOP_PK16=1 to select it.
 #ifndef MSPCG_HOP_PK16
-#define MSPCG_HOP_PK16 1
+#define MSPCG_HOP_PK16 0
 #endif
 #ifndef MSPCG_HOP_MFMA_WAVES
 #define MSPCG_HOP_MFMA_WAVES 4

@@ -57,17 +57,13 @@ def fp16_bar(n_roundings: int) -> float:
 
 
 # The FP16 block operator K stores p, B p, u, y, v and w once each and every
-# hop reads FP16 links: 7 stored roundings.  Each of its four hops also
-# projects and multiplies by the link in FP16 arithmetic (about one unit per
-# hop: every direction's product carries a few roundings of 2^-11, and the
-# eight directions, with independent errors, are summed in FP32): 11 units.
-# l local CG iterations store rho and p at the start and B p, u, y, v and rho
-# per iteration, with four hops each: 2 + 9 l units.  A single 5D entry may
-# collect the whole error of its 24 components: site bars are sqrt(24) times
-# the norm bars.
+# hop reads FP16 links: 7 stored roundings (the arithmetic is FP32).  l local
+# CG iterations store rho and p at the start and B p, u, y, v and rho per
+# iteration: 2 + 5 l.  A single 5D entry may collect the whole error of its 24
+# components: site bars are sqrt(24) times the norm bars.
 def k16_bars():
-    return fp16_bar(11), 24 ** 0.5 * fp16_bar(11)
+    return fp16_bar(7), 24 ** 0.5 * fp16_bar(7)
 
 
 def cg16_bars(l: int):
-    return fp16_bar(2 + 9 * l), 24 ** 0.5 * fp16_bar(2 + 9 * l)
+    return fp16_bar(2 + 5 * l), 24 ** 0.5 * fp16_bar(2 + 5 * l)

@@ -255,7 +255,7 @@ def test_schur_complement_matches_dense_block_elimination(p):
 @pytest.mark.parametrize("p", [SHAMIR, MOBIUS])
 def test_cg_solution_matches_dense_direct_solve(p):
     """Schur normal-equation CG + reconstruction solves D x = b (dense check at
-    2^4 x Ls=4, the spec dense pin)."""
+    2^4 x Ls=4, the dense direct-solve pin)."""
     dims, Ls = (2, 2, 2, 2), 4
     act = _act(dims, Ls, p)
     U = synth.gauge_field(dims, 0.3, 18)
