@@ -760,38 +760,54 @@ int solve_batch(mspcg_ctx* const* cs, int n, const void* const* b, void* const* 
                 return e;
             batch_multi = bprec->multi;
         }
+        // One outer iteration of every system not yet finished.  Captured, a
+        // finished system's kernels are left out of the graph altogether (its
+        // device done flag also makes them return at once, which is what the
+        // systems that finish between two captures rely on).
         auto iterate_all = [&](bool eager) -> int {
             if (!together) {
                 for (int i = 0; i < n; ++i) {
                     Solver& S = *sv[i];
-                    if (S.bb == 0.0 || (eager && (S.finished || S.s.done))) continue;
+                    if (S.bb == 0.0 || S.finished || (eager && S.s.done)) continue;
                     if ((e = S.iterate(st))) return e;
                 }
                 return 0;
             }
             for (int i : act)
-                if ((e = sv[i]->iterate_pre(st))) return e;
+                if (!sv[i]->finished && (e = sv[i]->iterate_pre(st))) return e;
             for (size_t j = 0; j < act.size(); ++j) dots[j] = PrecondDots{rr[j], qq[j], 0};
             if ((e = bprec->apply(ps[act[0]].inner_iters, rr.data(), zz.data(), dots.data(), st)))
                 return e;
             for (size_t j = 0; j < act.size(); ++j)
-                if ((e = sv[act[j]]->iterate_post(st, dots[j].np))) return e;
+                if (!sv[act[j]]->finished && (e = sv[act[j]]->iterate_post(st, dots[j].np)))
+                    return e;
+            return 0;
+        };
+        // the set of unfinished systems the current graph was captured for
+        std::vector<char> captured(n, 0);
+        auto capture = [&]() -> int {
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
+            exec = nullptr;
+            graph = nullptr;
+            for (int i = 0; i < n; ++i) captured[i] = !sv[i]->finished;
+            MSPCG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            if ((e = iterate_all(false))) {
+                (void)hipStreamEndCapture(st, &graph);
+                return e;
+            }
+            MSPCG_HIP(hipStreamEndCapture(st, &graph));
+            MSPCG_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
             return 0;
         };
         // one eager iteration creates every lazily allocated buffer before capture
         if ((e = iterate_all(true))) return e;
         MSPCG_HIP(hipStreamSynchronize(st));
-        MSPCG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        if ((e = iterate_all(false))) {
-            (void)hipStreamEndCapture(st, &graph);
-            return e;
-        }
-        MSPCG_HIP(hipStreamEndCapture(st, &graph));
-        MSPCG_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        if ((e = capture())) return e;
         const int check = p->check_every > 0 ? p->check_every : 4;
         int replays = 1;
         while (true) {
-            bool all = true;
+            bool all = true, changed = false;
             for (int i = 0; i < n; ++i) {
                 Solver& S = *sv[i];
                 if (S.finished) continue;
@@ -804,6 +820,8 @@ int solve_batch(mspcg_ctx* const* cs, int n, const void* const* b, void* const* 
                 for (int i = 0; i < n; ++i) sv[i]->finished = true;
                 break;
             }
+            for (int i = 0; i < n; ++i) changed = changed || (captured[i] && sv[i]->finished);
+            if (changed && (e = capture())) return e;
             for (int k = 0; k < check && replays < p->maxiter; ++k, ++replays)
                 MSPCG_HIP(hipGraphLaunch(exec, st));
         }
