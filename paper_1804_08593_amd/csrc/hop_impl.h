@@ -336,6 +336,17 @@ constexpr int hop_min_waves() {
     return (S::has_scale && !EPA && !CG && LS == 8) ? 6 : MSPCG_HOP_MINWAVES;
 }
 
+// The persistent multi-lattice kernel wraps hop_body in its work-list loop,
+// which left alone costs the FP16 Ls = 16 variants one wave per SIMD against
+// the plain launch (98-111 VGPRs, 4 waves); hold them to the plain kernel's
+// 5 (at Ls = 12 the same cap spills 116-184 bytes per lane).
+template <class S, int LS, bool EPA, bool CG>
+constexpr int multi_min_waves() {
+    return S::has_scale && LS == 16 && hop_min_waves<S, LS, EPA, CG>() < 5
+               ? 5
+               : hop_min_waves<S, LS, EPA, CG>();
+}
+
 // LDS layout of one hop workgroup (SPB sites x LS lanes).
 template <class S, int LS>
 struct HopShape {
@@ -911,7 +922,7 @@ long hop_grid_x(long Vh, int Ls) {
 // One launch over a work list of several lattices that share Ls (launch
 // bounds and LDS as for one lattice's hop).
 template <class S, int LS, bool DAG, bool EPH, bool EPA, bool CG>
-__global__ __launch_bounds__(256, (hop_min_waves<S, LS, EPA, CG>())) void multi_hop_kernel(
+__global__ __launch_bounds__(256, (multi_min_waves<S, LS, EPA, CG>())) void multi_hop_kernel(
     const MultiHop<S>* __restrict__ m) {
     __shared__ __attribute__((aligned(16))) unsigned char smem[HopShape<S, LS>::LDS_BYTES];
     const int n = m->n;
