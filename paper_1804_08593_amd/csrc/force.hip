@@ -14,15 +14,14 @@
 // sum above contracts two half spinors: P = sum_s h-(b(x+mu)) h-(a(x))^+ and
 // Q = sum_s h+(b(x)) h+(a(x+mu))^+ with h_sig(psi) = psi_up + sig e_mu psi_dn
 // (two spin rows of three colours each).
-// A workgroup of one wave takes 64/Ls sites, one lane per (site, s).  For
-// P, every lane keeps its a(x) in registers and, per direction, loads
-// b(x+mu) and forms its slice's 3x3 partial; neighbouring slices are added
-// across lanes, the pair sums go through LDS and are summed over s in a
-// fixed order by one lane per (site, entry).  Q the
-// same way with b(x) kept.  Then one lane per (site, direction, entry)
-// writes that entry of F and of the gradient.  Spinor loads are 16-byte chunks of
-// consecutive s, as in the hop, and each field is read once per direction
-// that needs it.
+// A workgroup of one wave takes 64/Ls sites, one lane per (site, s).  For P,
+// every lane keeps its a(x) in registers and, per direction, loads b(x+mu)
+// and forms its slice's 3x3 partial; neighbouring slices are added across
+// lanes, the pair sums go through LDS and are summed over s in a fixed order
+// by one lane per (site, entry).  Q the same way with b(x) kept.  Then one
+// lane per (site, direction, entry) writes that entry of F and of the
+// gradient.  Spinor loads are 16-byte chunks of consecutive s, as in the hop,
+// and each field is read once per direction that needs it.
 #include <string.h>
 
 #include "ctx.h"
@@ -31,7 +30,7 @@ namespace mspcg {
 
 namespace {
 
-// h = psi_up + SIG e_mu psi_dn (chiral basis, see hop.hip): the two spin rows
+// h = psi_up + SIG e_mu psi_dn (chiral basis, as project() in hop_impl.h): the two spin rows
 // that (1 + SIG g_mu) keeps
 template <int SIG>
 __device__ __forceinline__ void proj_half(int mu, const cx<double> (&p)[12], cx<double> (&h)[6]) {
