@@ -5,7 +5,7 @@ A step is one pass of the whole hot path on the 24^3x48, Ls=16 Moebius
 workload (b=1.5, c=0.5, M5=1.8, mf=0.005, links exp(0.2 i H)): the even-odd
 RHS preparation, a plain FP64 CG solve to a true residual of 1e-10, a
 mixed-precision CG solve (FP32 iterations, FP64 reliable updates), an MSPCG
-solve (16 blocks of 12^3x24, 6 local iterations, FP16 storage, FP16 link products)
+solve (16 blocks of 12^3x24, 6 local iterations, FP16 storage / FP32 math)
 to the same residual, the same MSPCG with the block shape picked by the
 library's blocking autotuner, and the odd-site reconstruction.  Inputs are
 seeded synthetic fields already resident in HBM when the timed region starts;

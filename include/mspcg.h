@@ -98,8 +98,7 @@ enum {
 enum {
     MSPCG_FP64 = 0,
     MSPCG_FP32 = 1,
-    MSPCG_FP16 = 2  /* FP16 storage of spinors (per-(x,s) FP32 scale) and links; the hops'
-                       spin projection and link product in FP16, everything else in FP32 */
+    MSPCG_FP16 = 2  /* FP16 storage of spinors (per-(x,s) FP32 scale) and links, FP32 math */
 };
 
 /* Solvers. */
