@@ -312,12 +312,28 @@ def batch_compare(args):
                           "seconds": round(float(np.median(times)), 4),
                           "outer_iters": [st["outer_iters"] for st in sts],
                           "true_rel_resid": [st["true_rel_resid"] for st in sts]}), flush=True)
-    # each lattice alone (eager solves), for the total of separate solves
+    # each lattice alone: eager mspcg_solve, and a one-system solve_batch
+    # (graph-replayed iteration) with per-lattice and with persistent block
+    # hops; median of 3 after one warm-up
     tot = 0.0
-    for c, b in zip(ctxs, bs):
-        x = torch.zeros_like(b)
-        c.solve(b, x, base)
-        tot += c.solve(b, x, base)["seconds"]
+    for (d, Ls, mf), c, b in zip(BATCH, ctxs, bs):
+        row = {"lattice": list(d), "Ls": Ls}
+        for mode in ("eager", "graph_per_lattice", "graph_persistent"):
+            times = []
+            for rep in range(4):
+                x = torch.zeros_like(b)
+                if mode == "eager":
+                    st = c.solve(b, x, base)
+                else:
+                    pb = mspcg.make_params(tol=args.tol, maxiter=3000, solver=mspcg.SOLVER_MSPCG,
+                                           inner_iters=args.inner_iters, inner_prec=mspcg.FP16,
+                                           batch_kernels=1 if mode == "graph_per_lattice" else 0)
+                    st = mspcg.solve_batch([c], [b], [x], pb)[0]
+                if rep:
+                    times.append(st["seconds"])
+            row[mode + "_seconds"] = round(float(np.median(times)), 4)
+        tot += row["eager_seconds"]
+        print(json.dumps(row), flush=True)
     print(json.dumps({"separate_solves_seconds": round(tot, 4)}), flush=True)
 
 
@@ -354,6 +370,26 @@ def sweep_readings(ctx, w, bd, x, args, log):
                    "true_rel_resid": st["true_rel_resid"]}
             print(json.dumps(row), flush=True)
             log(f"[sweep] {name} l={l}: {st['outer_iters']} it {st['seconds']:.3f} s")
+
+
+def tile_sweep(ctx, w, bd, x, args, log):
+    """FP64 dslash time for each traversal tile in --tiles (AxBxCxD,...):
+    60 plain CG iterations with per-class HIP-event timing per tile."""
+    from paper_1804_08593_amd import mspcg
+
+    for t in args.tiles.split(","):
+        tile = tuple(int(v) for v in t.split("x"))
+        ctx.set_tuning(1, tile, (0, 0, 0, 0), (0, 0, 0, 0))
+        p = mspcg.make_params(tol=1e-30, maxiter=60, solver=mspcg.SOLVER_CG, timing=True)
+        ctx.solve(bd, x, p, allow_noconv=True)
+        st = ctx.solve(bd, x, p, allow_noconv=True)
+        row = {"workload": args.workload, "fp64_tile": list(tile)}
+        for k in ("hop64", "hopcg"):
+            n = st["kernel_launches"][k]
+            if n:
+                row[k + "_avg_us"] = round(1e3 * st["kernel_ms"][k] / n, 1)
+        print(json.dumps(row), flush=True)
+        log(f"[tiles] {tile}: {row}")
 
 
 def multisplit_compare(ctx, w, bd, x, args, log, sweeps=400):
@@ -405,6 +441,8 @@ def main():
                     help="instead of the bench line: MSPCG with the workload's blocks for "
                          "every block reading (Dirichlet, pad 1, split Schur, literal) and "
                          "l = 2..8, one JSON line per solve")
+    ap.add_argument("--tiles", default=None,
+                    help="FP64 dslash time per traversal tile AxBxCxD,... on the workload, then exit")
     ap.add_argument("--multisplit", action="store_true",
                     help="multisplitting sweeps beside MSPCG on the workload, then exit")
     ap.add_argument("--no-autotune", action="store_true")
@@ -464,6 +502,9 @@ def main():
         return
     if args.multisplit:
         multisplit_compare(ctx, w, bd, x, args, log)
+        return
+    if args.tiles:
+        tile_sweep(ctx, w, bd, x, args, log)
         return
 
     p_cg = mspcg.make_params(tol=args.tol, maxiter=20000, solver=mspcg.SOLVER_CG, timing=True)
