@@ -35,8 +35,11 @@ def _random_T(rng):
     return T / np.linalg.norm(T)
 
 
-def test_force_matches_oracle_force():
-    dims, Ls = (8, 4, 4, 8), 8
+@pytest.mark.parametrize("dims,Ls", [((8, 4, 4, 8), 8), ((4, 4, 4, 8), 16), ((4, 8, 4, 4), 12),
+                                     ((6, 4, 4, 4), 6)])
+def test_force_matches_oracle_force(dims, Ls):
+    """Every lane grouping of the force kernel: 64 / Ls sites per workgroup
+    (8, 4, 5 and 10 sites, Ls = 12 and 6 leaving idle lanes)."""
     act, U, ctx = setup(dims, Ls, MOB["M5"], 0.05, MOB["b"], MOB["c"], eps=0.25, gseed=41)
     phi, X, Y = _force_inputs(ctx, act, 42)
     F = torch.zeros(ctx.gshape, dtype=torch.complex128, device="cuda")
