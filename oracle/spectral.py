@@ -15,7 +15,8 @@ low precision) is enough.  This module measures that on small lattices:
   * sloppy K_l: Ritz values of K_l^-1 A from the outer PCG's coefficients
     (Lanczos tridiagonal), and the outer iteration count, against l.
 
-Run `python -m oracle.spectral` to print the tables (a few minutes).
+Run `python -m oracle.spectral` to print the tables (a few minutes), and
+`python -m oracle.spectral --lanczos` for the sloppy-K_l table on 8^4 x Ls=4.
 """
 from __future__ import annotations
 
@@ -206,5 +207,38 @@ def study(out=sys.stdout):
     w(f"\n(study time {time.time() - t0:.0f} s)\n")
 
 
+def lanczos_study(out=sys.stdout, dims=(8, 8, 8, 8), Ls=4, blocks=((4, 4, 4, 4), (8, 8, 4, 4)),
+                  ls=(1, 2, 4, 6, 8)):
+    """Sloppy K_l on a lattice too large for dense algebra: outer flexible
+    PCG iterations to 1e-10 and the Ritz values of K_l^-1 A from its
+    coefficients, against l, with plain CG (l = 0) for A itself."""
+    from paper_1804_08593_amd import synth
+    from . import cg
+    t0 = time.time()
+    w = out.write
+    act = Action(dims, Ls, 1.8, 0.01, 1.5, 0.5)
+    U = synth.gauge_field(dims, 0.25, 4012)
+    _, bhat = prepare(act, U, synth.fermion_field(dims, Ls, 4013))
+    w(f"## Sloppy local solves K_l, {dims} x Ls={Ls}, literal blocks, outer flexible PCG to "
+      f"1e-10 (Ritz values from the Lanczos coefficients)\n\n")
+    w("| blocks | l | outer iterations | Ritz min | Ritz max | kappa_eff |\n|---|---|---|---|---|---|\n")
+    _, info0 = cg(act, U, bhat, tol=1e-10)
+    r0 = ritz_from_coef(info0.coef)
+    w(f"| - | 0 | {info0.iters} | {_fmt(r0[0])} | {_fmt(r0[-1])} | {_fmt(r0[-1] / r0[0])} |\n")
+    out.flush()
+    for blk in blocks:
+        nb = int(np.prod([dims[m] // blk[m] for m in range(4)]))
+        for l in ls:
+            _, info = mspcg(act, U, bhat, blk, l, tol=1e-10)
+            r = ritz_from_coef(info.coef)
+            w(f"| {nb} | {l} | {info.iters} | {_fmt(r[0])} | {_fmt(r[-1])} | "
+              f"{_fmt(r[-1] / r[0])} |\n")
+            out.flush()
+    w(f"\n(study time {time.time() - t0:.0f} s)\n")
+
+
 if __name__ == "__main__":
-    study()
+    if "--lanczos" in sys.argv:
+        lanczos_study()
+    else:
+        study()
