@@ -345,6 +345,21 @@ READINGS = [  # (name, pad, form): the block operator A_s of the preconditioner
 ]
 
 
+def ritz_range(coef):
+    """Extreme eigenvalues of the Lanczos tridiagonal of (P)CG coefficients
+    (alpha_k, beta_k): T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},
+    T_j,j+1 = sqrt(beta_j)/alpha_j."""
+    import scipy.linalg
+
+    c = np.asarray(coef, dtype=float)
+    a, b = c[:, 0], c[:, 1]
+    d = 1.0 / a
+    d[1:] += b[:-1] / a[:-1]
+    e = np.sqrt(np.maximum(b[:-1], 0.0)) / a[:-1]
+    ev = scipy.linalg.eigh_tridiagonal(d, e, eigvals_only=True)
+    return float(ev[0]), float(ev[-1])
+
+
 def sweep_readings(ctx, w, bd, x, args, log):
     """Outer iterations (the paper's global iterations, Sec. 3) and time of
     MSPCG for each block reading and l, beside plain CG, on one GPU."""
@@ -352,18 +367,22 @@ def sweep_readings(ctx, w, bd, x, args, log):
 
     p_cg = mspcg.make_params(tol=args.tol, maxiter=20000, solver=mspcg.SOLVER_CG)
     ctx.solve(bd, x, p_cg)
-    cg = ctx.solve(bd, x, p_cg)
+    cg = ctx.solve(bd, x, p_cg, coef=20000)
+    lo, hi = ritz_range(cg["cg_coef"])
     print(json.dumps({"workload": args.workload, "solver": "cg", "outer_iters": cg["outer_iters"],
-                      "seconds": round(cg["seconds"], 4)}), flush=True)
+                      "seconds": round(cg["seconds"], 4), "ritz": [lo, hi],
+                      "kappa_eff": round(hi / lo, 1)}), flush=True)
     for name, pad, form in READINGS:
         for l in (2, 3, 4, 6, 8):
             p = mspcg.make_params(tol=args.tol, maxiter=20000, solver=mspcg.SOLVER_MSPCG,
                                   block=w["block"], pad=pad, form=form, inner_iters=l,
                                   inner_prec=mspcg.FP16)
             ctx.solve(bd, x, p)  # domain set-up, untimed
-            st = ctx.solve(bd, x, p)
+            st = ctx.solve(bd, x, p, coef=20000)
+            lo, hi = ritz_range(st["cg_coef"])
             row = {"workload": args.workload, "solver": "mspcg", "reading": name,
                    "block": list(w["block"]), "l": l, "outer_iters": st["outer_iters"],
+                   "ritz": [lo, hi], "kappa_eff": round(hi / lo, 2),
                    "g": round(cg["outer_iters"] / st["outer_iters"], 3),
                    "seconds": round(st["seconds"], 4),
                    "speedup_vs_cg": round(cg["seconds"] / st["seconds"], 3),

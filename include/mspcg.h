@@ -191,9 +191,11 @@ typedef struct {
     double kernel_ms[MSPCG_KC_COUNT];     /* timing = 1: summed kernel time per class */
     long kernel_launches[MSPCG_KC_COUNT];
     double kernel_bytes[MSPCG_KC_COUNT];  /* algorithmic bytes of those launches */
-    double* cg_coef;       /* caller buffer (may be NULL), plain CG only: (alpha_k, beta_k)
-                              per iteration k, 2 doubles each; the Lanczos tridiagonal
-                              they define bounds the spectrum of A from inside */
+    double* cg_coef;       /* caller buffer (may be NULL), plain CG and MSPCG: (alpha_k,
+                              beta_k) per iteration k, 2 doubles each (MSPCG: the flexible
+                              beta, 0 after a restart); the Lanczos tridiagonal they define
+                              bounds the spectrum of A (plain CG) from inside, and estimates
+                              that of K_l^-1 A (MSPCG; exact for an exact, fixed K) */
     int cg_coef_cap;       /* iterations the buffer holds */
     int cg_coef_len;
     int batch_persistent;  /* mspcg_solve_batch: 1 when the local solves' block hops ran as

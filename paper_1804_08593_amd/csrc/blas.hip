@@ -147,12 +147,17 @@ __global__ void cg_alpha_kernel(DevScalars* sc, const double* partials, int npar
 
 // Flexible (Polak-Ribiere) beta from <z_new, r_new> and <z_new, q>:
 // r_old = r_new + alpha q, so <z_new, r_new - r_old> = -alpha <z_new, q>.
-__global__ void fpcg_beta_kernel(DevScalars* sc, const double* partials, int nparts) {
+__global__ void fpcg_beta_kernel(DevScalars* sc, const double* partials, int nparts, double* hist,
+                                 int hist_cap) {
     if (sc->done) return;
     const double zr = block_sum_all(partials, nparts);
     const double zq = block_sum_all(partials + nparts, nparts);
     if (threadIdx.x == 0) {
         sc->beta = sc->zr != 0.0 ? -sc->alpha * zq / sc->zr : 0.0;
+        // the flexible beta of the iteration just completed replaces the
+        // residual ratio cg_beta_kernel recorded for it
+        const int k = sc->iter - 1;
+        if (hist && k >= 0 && k < hist_cap) hist[3 * k + 2] = sc->beta;
         sc->zr = zr;
         sc->zq = zq;
         if (!(zr > 0.0) || !isfinite(zr)) {
@@ -344,8 +349,10 @@ int launch_cg_alpha(DevScalars* sc, const double* partials, int nparts, hipStrea
     return last_error();
 }
 
-int launch_fpcg_beta(DevScalars* sc, const double* partials, int nparts, hipStream_t st) {
-    hipLaunchKernelGGL(fpcg_beta_kernel, dim3(1), dim3(kThreads), 0, st, sc, partials, nparts);
+int launch_fpcg_beta(DevScalars* sc, const double* partials, int nparts, double* hist,
+                     int hist_cap, hipStream_t st) {
+    hipLaunchKernelGGL(fpcg_beta_kernel, dim3(1), dim3(kThreads), 0, st, sc, partials, nparts,
+                       hist, hist_cap);
     return last_error();
 }
 

@@ -170,7 +170,8 @@ int launch_reduce_domains(const double* partials, int ndom, int nparts, double* 
 // CG scalar updates (single thread kernels)
 int launch_cg_alpha(DevScalars* sc, const double* partials, int nparts, hipStream_t st,
                     int flexible = 0);
-int launch_fpcg_beta(DevScalars* sc, const double* partials, int nparts, hipStream_t st);
+int launch_fpcg_beta(DevScalars* sc, const double* partials, int nparts, double* hist,
+                     int hist_cap, hipStream_t st);
 int launch_cg_beta(DevScalars* sc, const double* partials, int nparts, double* hist,
                    int hist_cap, hipStream_t st);
 

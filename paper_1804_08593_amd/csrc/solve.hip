@@ -123,7 +123,8 @@ struct Solver {
         st->resid_history_len = 0;
         st->cg_coef_len = 0;
         const bool want_h = st->resid_history && st->resid_history_cap > 0;
-        const bool want_c = st->cg_coef && st->cg_coef_cap > 0 && p->solver == MSPCG_SOLVER_CG;
+        const bool want_c = st->cg_coef && st->cg_coef_cap > 0 &&
+                            (p->solver == MSPCG_SOLVER_CG || p->solver == MSPCG_SOLVER_MSPCG);
         const int cap_h = want_h ? st->resid_history_cap : 0;
         const int cap_c = want_c ? st->cg_coef_cap : 0;
         int n = cap_h > cap_c ? cap_h : cap_c;
@@ -230,7 +231,7 @@ struct MSPCGSolver : Solver {
         if ((e = precond_apply_flag<S>(c, l, cfield(r), z, &c->sc->done, st))) return e;
         MSPCG_HIP(hipMemsetAsync(pp.data, 0, (size_t)12 * c->Nh * sizeof(double2), st));
         if (launch_dot2(z.data, r.data, r.data, c->Nh, c->partials, npb, st)) return MSPCG_EHIP;
-        if (launch_fpcg_beta(c->sc, c->partials, (int)npb, st)) return MSPCG_EHIP;
+        if (launch_fpcg_beta(c->sc, c->partials, (int)npb, c->hist, cap, st)) return MSPCG_EHIP;
         return 0;
     }
     int init(hipStream_t st) override {
@@ -292,7 +293,7 @@ struct MSPCGSolver : Solver {
             if (launch_dot2(z.data, r.data, q.data, c->Nh, c->partials, npb, st)) return MSPCG_EHIP;
             np = npb;
         }
-        if (launch_fpcg_beta(c->sc, c->partials, (int)np, st)) return MSPCG_EHIP;
+        if (launch_fpcg_beta(c->sc, c->partials, (int)np, c->hist, cap, st)) return MSPCG_EHIP;
         return 0;
     }
     void batch_io(CField<F64>& r_, Field<F64>& z_, CField<F64>& q_) override {

@@ -250,7 +250,7 @@ class Context:
 
     def solve(self, b, x, params: SolveParams, history=0, stream=None, allow_noconv=False,
               coef=0):
-        """history / coef: iterations of residual history / plain-CG coefficients to return."""
+        """history / coef: iterations of residual history / (P)CG coefficients to return."""
         st = SolveStats()
         hist = cf = None
         if history:

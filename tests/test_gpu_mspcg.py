@@ -6,6 +6,7 @@ import torch
 
 import oracle as O
 from paper_1804_08593_amd import mspcg, synth
+from oracle.spectral import ritz_from_coef
 from tests.gpu_util import cg16_bars, dev, host, k16_bars, relerr, say, setup, site_err
 
 pytestmark = pytest.mark.gpu
@@ -107,6 +108,31 @@ def test_mspcg_solve_matches_oracle(prec):
         _, info = O.solve(act, U, b, tol=1e-10, precond=(blk, 4, "literal"))
         assert abs(st["outer_iters"] - info.iters) <= 1
     assert st["inner_iters_total"] >= 4 * st["outer_iters"]
+
+
+def test_mspcg_coefficients_match_oracle():
+    """The outer flexible PCG's (alpha, beta) per iteration, which define the
+    Lanczos estimate of the spectrum of K_l^-1 A, against the oracle's MSPCG
+    with the same FP64 local solves (literal blocks, l = 4)."""
+    dims, Ls, blk = GEOM
+    act, U, ctx = setup(dims, Ls, 1.8, 0.05, 1.5, 0.5, gseed=23)
+    bh = O.parity_mask(act, synth.fermion_field(dims, Ls, 24), 0)
+    x = torch.zeros(ctx.fshape, dtype=torch.complex128, device="cuda")
+    st = ctx.solve(dev(bh), x, mspcg.make_params(tol=1e-10, maxiter=500,
+                                                 solver=mspcg.SOLVER_MSPCG, block=blk, pad=2,
+                                                 inner_iters=4, inner_prec=mspcg.FP64,
+                                                 rhs_normal=True), coef=500)
+    _, info = O.mspcg(act, U, bh, blk, 4, tol=1e-10)
+    got, ref = np.asarray(st["cg_coef"]), np.asarray(info.coef)
+    n = min(len(got), len(ref))
+    say(f"MSPCG coefficients: GPU {len(got)}, oracle {len(ref)} iterations")
+    assert n >= 10 and abs(len(got) - len(ref)) <= 1
+    early = np.abs(got[:10] - ref[:10]) / np.abs(ref[:10]).max(axis=0)
+    assert early.max() <= 1e-9
+    rg, rr = ritz_from_coef(got[:n]), ritz_from_coef(ref[:n])
+    lg, hg, lr, hr = rg[0], rg[-1], rr[0], rr[-1]
+    say(f"  Ritz range GPU [{lg:.4g}, {hg:.4g}], oracle [{lr:.4g}, {hr:.4g}]")
+    assert abs(lg - lr) <= 1e-3 * lr and abs(hg - hr) <= 1e-3 * hr
 
 
 def test_mixed_precision_cg():
