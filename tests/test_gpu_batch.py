@@ -71,12 +71,13 @@ MULTI = [((8, 4, 4, 8), 8, 0.05, (4, 4, 4, 4)), ((4, 4, 4, 8), 12, 0.01, (4, 4, 
          ((8, 8, 4, 8), 16, 0.1, (4, 4, 4, 4))]
 
 
-def test_persistent_multi_lattice_launch_matches_per_lattice_launches():
+@pytest.mark.parametrize("prec", [mspcg.FP16, mspcg.FP32, mspcg.FP64])
+def test_persistent_multi_lattice_launch_matches_per_lattice_launches(prec):
     sys = [_make(d, Ls, mf, 0.25, 80 + i, 90 + i, blk) for i, (d, Ls, mf, blk) in enumerate(MULTI)]
     out = {}
     for kern in (0, 1):
         prm = mspcg.make_params(tol=1e-10, maxiter=2000, solver=mspcg.SOLVER_MSPCG,
-                                inner_iters=4, inner_prec=mspcg.FP16, batch_kernels=kern)
+                                inner_iters=4, inner_prec=prec, batch_kernels=kern)
         xs = [torch.zeros_like(b) for _, _, b in sys]
         sts = mspcg.solve_batch([c for c, _, _ in sys], [b for _, _, b in sys], xs, prm,
                                 history=2000)
