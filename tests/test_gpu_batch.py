@@ -52,6 +52,8 @@ def test_batch_equals_individual_solves(solver):
         xs = [torch.zeros_like(b) for _, _, b in sys]
         sts = mspcg.solve_batch([c for c, _, _ in sys], [b for _, _, b in sys], xs, prm,
                                 history=2000)
+        # Ls = 4 has no persistent multi-lattice kernel: per-lattice launches
+        assert not any(st["batch_persistent"] for st in sts)
         for i, ((xr, sr), xb, sb) in enumerate(zip(ref, xs, sts)):
             say(f"rep {rep} system {i}: iters {sb['outer_iters']} (eager {sr['outer_iters']})")
             assert sb["converged"] and sb["true_rel_resid"] <= 1e-10
