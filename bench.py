@@ -391,6 +391,32 @@ def sweep_readings(ctx, w, bd, x, args, log):
             log(f"[sweep] {name} l={l}: {st['outer_iters']} it {st['seconds']:.3f} s")
 
 
+def sweep_blocks(ctx, w, bd, x, args, log):
+    """MSPCG (literal blocks, FP16 local solves) for several block shapes and
+    l on the workload, beside plain CG; best of two solves without per-kernel
+    timing."""
+    from paper_1804_08593_amd import mspcg
+
+    L = w["dims"]
+    shapes = [tuple(w["block"]), (L[0], L[1], L[2] // 2, L[3] // 2), (L[0], L[1], L[2], L[3] // 2),
+              (L[0] // 2, L[1], L[2], L[3])]
+    p_cg = mspcg.make_params(tol=args.tol, maxiter=20000, solver=mspcg.SOLVER_CG)
+    cg = min((ctx.solve(bd, x, p_cg) for _ in range(2)), key=lambda st: st["seconds"])
+    print(json.dumps({"workload": args.workload, "solver": "cg", "outer_iters": cg["outer_iters"],
+                      "seconds": round(cg["seconds"], 4)}), flush=True)
+    for blk in shapes:
+        for l in (2, 3, 4, 6, 8):
+            p = mspcg.make_params(tol=args.tol, maxiter=20000, solver=mspcg.SOLVER_MSPCG,
+                                  block=blk, pad=2, inner_iters=l, inner_prec=mspcg.FP16)
+            ctx.solve(bd, x, p)  # domain set-up
+            st = min((ctx.solve(bd, x, p) for _ in range(2)), key=lambda r: r["seconds"])
+            row = {"workload": args.workload, "block": list(blk), "l": l,
+                   "outer_iters": st["outer_iters"], "seconds": round(st["seconds"], 4),
+                   "speedup_vs_cg": round(cg["seconds"] / st["seconds"], 3)}
+            print(json.dumps(row), flush=True)
+            log(f"[blocks] {blk} l={l}: {st['outer_iters']} it {st['seconds']:.3f} s")
+
+
 def tile_sweep(ctx, w, bd, x, args, log):
     """FP64 dslash time for each traversal tile in --tiles (AxBxCxD,...):
     60 plain CG iterations with per-class HIP-event timing per tile."""
@@ -460,6 +486,8 @@ def main():
                     help="instead of the bench line: MSPCG with the workload's blocks for "
                          "every block reading (Dirichlet, pad 1, split Schur, literal) and "
                          "l = 2..8, one JSON line per solve")
+    ap.add_argument("--sweep-blocks", action="store_true",
+                    help="MSPCG time per block shape and l on the workload, then exit")
     ap.add_argument("--tiles", default=None,
                     help="FP64 dslash time per traversal tile AxBxCxD,... on the workload, then exit")
     ap.add_argument("--multisplit", action="store_true",
@@ -524,6 +552,9 @@ def main():
         return
     if args.tiles:
         tile_sweep(ctx, w, bd, x, args, log)
+        return
+    if args.sweep_blocks:
+        sweep_blocks(ctx, w, bd, x, args, log)
         return
 
     p_cg = mspcg.make_params(tol=args.tol, maxiter=20000, solver=mspcg.SOLVER_CG, timing=True)
