@@ -296,7 +296,9 @@ int mspcg_pseudofermion_action(mspcg_ctx* ctx, const void* phi_dev, void* X_dev,
  * with the same parameters: the paper's several nodes each solving their own
  * sub-problem (Sec. 2.1, Fig. 1), here several lattices sharing one GPU.  The
  * outer iterations of all still-active systems are interleaved on one
- * stream; arguments as for mspcg_solve, per system.  stats: array of n (may
+ * stream; arguments as for mspcg_solve, per system.  A system whose
+ * right-hand side is zero gets x = 0 with zero iterations and takes no part
+ * in the iterations of the others; n = 0 is a no-op.  stats: array of n (may
  * be NULL). */
 int mspcg_solve_batch(mspcg_ctx* const* ctxs, int n, const void* const* b_dev, void* const* x_dev,
                       const mspcg_solve_params* params, mspcg_solve_stats* stats,

@@ -801,13 +801,19 @@ int solve_batch(mspcg_ctx* const* cs, int n, const void* const* b, void* const* 
             MSPCG_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
             return 0;
         };
-        // one eager iteration creates every lazily allocated buffer before capture
-        if ((e = iterate_all(true))) return e;
-        MSPCG_HIP(hipStreamSynchronize(st));
-        if ((e = capture())) return e;
+        // nothing to iterate (every right-hand side zero, or every warm start
+        // already converged): no eager pass and no graph
+        bool pending = false;
+        for (int i = 0; i < n; ++i) pending = pending || !sv[i]->finished;
         const int check = p->check_every > 0 ? p->check_every : 4;
         int replays = 1;
-        while (true) {
+        if (pending) {
+            // one eager iteration creates every lazily allocated buffer before capture
+            if ((e = iterate_all(true))) return e;
+            MSPCG_HIP(hipStreamSynchronize(st));
+            if ((e = capture())) return e;
+        }
+        while (pending) {
             bool all = true, changed = false;
             for (int i = 0; i < n; ++i) {
                 Solver& S = *sv[i];

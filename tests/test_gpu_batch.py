@@ -104,6 +104,51 @@ def test_persistent_multi_lattice_launch_matches_per_lattice_launches(prec):
     say(f"persistent vs per-lattice launches bitwise identical: {bitwise}")
 
 
+def test_persistent_batch_degenerate_members():
+    """Degenerate batches on the persistent path: a member with a zero
+    right-hand side (x = 0, no iterations, left out of the others' launches),
+    a batch of zero right-hand sides only, and a batch of one lattice against
+    its own eager solve and the oracle."""
+    sys = [_make(d, Ls, mf, 0.25, 80 + i, 90 + i, blk) for i, (d, Ls, mf, blk) in enumerate(MULTI)]
+    prm = mspcg.make_params(tol=1e-10, maxiter=2000, solver=mspcg.SOLVER_MSPCG, inner_iters=4,
+                            inner_prec=mspcg.FP16)
+    (c0, _, b0), (c1, _, b1), (c2, U2, b2) = sys
+    say("reference: lattices 0 and 2 batched on their own")
+    xr = [torch.zeros_like(b0), torch.zeros_like(b2)]
+    sr = mspcg.solve_batch([c0, c2], [b0, b2], xr, prm, history=2000)
+    say("lattice 1 with a zero right-hand side between them")
+    xs = [torch.zeros_like(b0), torch.ones_like(b1), torch.zeros_like(b2)]
+    sts = mspcg.solve_batch([c0, c1, c2], [b0, torch.zeros_like(b1), b2], xs, prm, history=2000)
+    assert sts[1]["converged"] and sts[1]["outer_iters"] == 0
+    assert torch.count_nonzero(xs[1]) == 0
+    for j, i in ((0, 0), (1, 2)):
+        say(f"  lattice {i}: {sts[i]['outer_iters']} it (without lattice 1: {sr[j]['outer_iters']})")
+        assert sts[i]["batch_persistent"] and sr[j]["batch_persistent"]
+        assert sts[i]["converged"] and sts[i]["true_rel_resid"] <= 1e-10
+        assert sts[i]["outer_iters"] == sr[j]["outer_iters"]
+        assert relerr(host(xs[i]), host(xr[j])) <= 1e-12
+    say("zero right-hand sides only")
+    xz = [torch.ones_like(b0), torch.ones_like(b1)]
+    sz = mspcg.solve_batch([c0, c1], [torch.zeros_like(b0), torch.zeros_like(b1)], xz, prm)
+    for st, x in zip(sz, xz):
+        assert st["converged"] and st["outer_iters"] == 0
+        assert torch.count_nonzero(x) == 0
+    say("one lattice: batch against eager solve and oracle")
+    xb = [torch.zeros_like(b2)]
+    sb = mspcg.solve_batch([c2], [b2], xb, prm, history=2000)[0]
+    xe = torch.zeros_like(b2)
+    se = c2.solve(b2, xe, prm, history=2000)
+    say(f"  batch {sb['outer_iters']} it, eager {se['outer_iters']} it")
+    assert sb["batch_persistent"] and sb["converged"]
+    assert sb["outer_iters"] == se["outer_iters"]
+    assert relerr(host(xb[0]), host(xe)) <= 1e-12
+    d, Ls, mf, _ = MULTI[2]
+    act = O.Action(d, Ls, 1.8, mf, 1.5, 0.5)
+    _, bhat = O.prepare(act, U2, host(b2))
+    r = bhat - O.normal(act, U2, O.parity_mask(act, host(xb[0]), 0))
+    assert np.sqrt(O.norm2(r) / O.norm2(bhat)) <= 1e-10 * 1.01
+
+
 C4_SHAPES = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 16), (12, 12, 12, 24),
              (16, 16, 16, 32), (20, 20, 20, 20)]
 C4_LSMF = [(8, 0.05), (12, 0.01), (16, 0.05), (8, 0.01), (12, 0.05), (16, 0.01)]
