@@ -594,6 +594,14 @@ def main():
             out["mspcg_tuned"] = ctx_t.solve(bd, x, p_mt)
         return out
 
+    def class_split(st):
+        """Per-class [launches, ms] of one solve and the share of its wall time
+        the classes cover."""
+        cl = {k: [st["kernel_launches"][k], round(v, 1)] for k, v in st["kernel_ms"].items()
+              if st["kernel_launches"][k]}
+        tot = sum(v for v in st["kernel_ms"].values())
+        return {"classes": cl, "kernel_share_of_wall": round(1e-3 * tot / st["seconds"], 3)}
+
     def describe(r):
         return ", ".join(f"{k} {v['outer_iters']} it {v['seconds']:.3f} s" for k, v in r.items())
 
@@ -670,14 +678,16 @@ def main():
                          "true_rel_resid": last["mspcg"]["true_rel_resid"],
                          "speedup_vs_cg": round(cg_s / ms_s, 3),
                          "outer_iter_reduction_g": round(last["cg"]["outer_iters"]
-                                                         / max(1, last["mspcg"]["outer_iters"]), 3)}
+                                                         / max(1, last["mspcg"]["outer_iters"]), 3),
+                         "kernel_time": class_split(last["mspcg"])}
     if run_mt:
         mt_s = float(np.median([r["mspcg_tuned"]["seconds"] for r in results]))
         line["mspcg_tuned_blocking"] = {"seconds": round(mt_s, 4), "blocking": tuned_block,
                                         "outer_iters": last["mspcg_tuned"]["outer_iters"],
                                         "inner_iters_total": last["mspcg_tuned"]["inner_iters_total"],
                                         "true_rel_resid": last["mspcg_tuned"]["true_rel_resid"],
-                                        "speedup_vs_cg": round(cg_s / mt_s, 3)}
+                                        "speedup_vs_cg": round(cg_s / mt_s, 3),
+                                        "kernel_time": class_split(last["mspcg_tuned"])}
     if run_ms and not args.no_fp64_inner:
         # the same MSPCG with FP64 local solves (untimed): its outer count is
         # the one the oracle's FP64 MSPCG reaches (within one iteration on the
