@@ -143,11 +143,19 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _ptr(t):
+def _ptr(t, numel=None, device=None):
+    """Device pointer of a field, after the checks the C ABI cannot make on a
+    bare pointer: complex128, on a HIP device, contiguous and, when given, the
+    element count and device index the context expects."""
     import torch
-    assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128, \
-        "fields are complex128 CUDA tensors"
-    assert t.is_contiguous()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.complex128:
+        raise TypeError("fields are complex128 tensors on a HIP device")
+    if not t.is_contiguous():
+        raise ValueError("fields must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"field has {t.numel()} elements where the context expects {numel}")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"field is on device {t.device.index}, the context on device {device}")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -182,6 +190,7 @@ class Context:
         self._h = h
         self.dims = tuple(int(x) for x in dims)
         self.Ls = int(Ls)
+        self.device = int(device)
         w = ctypes.c_int()
         _check(lib.mspcg_get_warnings(h, ctypes.byref(w)), "mspcg_get_warnings")
         self.warnings = w.value
@@ -221,17 +230,25 @@ class Context:
         Lx, Ly, Lz, Lt = self.dims
         return (4, Lt, Lz, Ly, Lx, 3, 3)
 
+    def _f(self, t):
+        """Pointer of a fermion field of this context (checked)."""
+        return _ptr(t, int(np.prod(self.fshape)), self.device)
+
+    def _g(self, t):
+        """Pointer of a link field of this context (checked)."""
+        return _ptr(t, int(np.prod(self.gshape)), self.device)
+
     def load_gauge(self, U, stream=None):
-        _check(load().mspcg_load_gauge(self._h, _ptr(U), _stream(stream)), "mspcg_load_gauge")
+        _check(load().mspcg_load_gauge(self._h, self._g(U), _stream(stream)), "mspcg_load_gauge")
 
     def apply(self, op, inp, out, prec=FP64, stream=None):
-        _check(load().mspcg_apply(self._h, int(op), int(prec), _ptr(inp), _ptr(out),
+        _check(load().mspcg_apply(self._h, int(op), int(prec), self._f(inp), self._f(out),
                                   _stream(stream)), "mspcg_apply")
         return out
 
     def apply_noalloc(self, op, inp, out, prec=FP64, stream=None):
         """mspcg_apply without device allocation (fixed per-GPU scratch)."""
-        _check(load().mspcg_apply_noalloc(self._h, int(op), int(prec), _ptr(inp), _ptr(out),
+        _check(load().mspcg_apply_noalloc(self._h, int(op), int(prec), self._f(inp), self._f(out),
                                           _stream(stream)), "mspcg_apply_noalloc")
         return out
 
@@ -244,7 +261,7 @@ class Context:
         _check(load().mspcg_set_blocking(self._h, ctypes.byref(b)), "mspcg_set_blocking")
 
     def precond(self, r, z, inner_iters, prec=FP16, stream=None):
-        _check(load().mspcg_precond(self._h, int(inner_iters), int(prec), _ptr(r), _ptr(z),
+        _check(load().mspcg_precond(self._h, int(inner_iters), int(prec), self._f(r), self._f(z),
                                     _stream(stream)), "mspcg_precond")
         return z
 
@@ -261,7 +278,7 @@ class Context:
             cf = (ctypes.c_double * (2 * int(coef)))()
             st.cg_coef = ctypes.cast(cf, ctypes.POINTER(ctypes.c_double))
             st.cg_coef_cap = int(coef)
-        rc = load().mspcg_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(params),
+        rc = load().mspcg_solve(self._h, self._f(b), self._f(x), ctypes.byref(params),
                                 ctypes.byref(st), _stream(stream))
         _check(rc, "mspcg_solve", allow=(ENOCONV,) if allow_noconv else ())
         return stats_dict(st, hist, rc, cf)
@@ -272,8 +289,8 @@ class Context:
         p = params if params is not None else make_params(tol=1e-12, maxiter=20000)
         S = ctypes.c_double()
         st = SolveStats()
-        rc = load().mspcg_pseudofermion_action(self._h, _ptr(phi), _ptr(X),
-                                               _ptr(dphi) if dphi is not None else None,
+        rc = load().mspcg_pseudofermion_action(self._h, self._f(phi), self._f(X),
+                                               self._f(dphi) if dphi is not None else None,
                                                ctypes.byref(p), ctypes.byref(S),
                                                ctypes.byref(st), _stream(stream))
         _check(rc, "mspcg_pseudofermion_action", allow=(ENOCONV,) if allow_noconv else ())
@@ -314,9 +331,9 @@ class Context:
 
     def force(self, X, Y, F=None, G=None, stream=None):
         """F: traceless Hermitian force per link; G: gradient w.r.t. the complex link."""
-        _check(load().mspcg_force(self._h, _ptr(X), _ptr(Y),
-                                  _ptr(F) if F is not None else None,
-                                  _ptr(G) if G is not None else None, _stream(stream)),
+        _check(load().mspcg_force(self._h, self._f(X), self._f(Y),
+                                  self._g(F) if F is not None else None,
+                                  self._g(G) if G is not None else None, _stream(stream)),
                "mspcg_force")
         return F, G
 
@@ -345,9 +362,11 @@ def stats_dict(st: SolveStats, hist=None, rc=OK, coef=None) -> dict:
 def solve_batch(ctxs, bs, xs, params: SolveParams, history=0, stream=None, allow_noconv=False):
     """Solve n independent systems together (hipGraph-replayed outer iterations)."""
     n = len(ctxs)
+    if len(bs) != n or len(xs) != n:
+        raise ValueError("one right-hand side and one solution per context")
     H = (ctypes.c_void_p * n)(*[c.handle for c in ctxs])
-    B = (ctypes.c_void_p * n)(*[_ptr(b) for b in bs])
-    X = (ctypes.c_void_p * n)(*[_ptr(x) for x in xs])
+    B = (ctypes.c_void_p * n)(*[c._f(b) for c, b in zip(ctxs, bs)])
+    X = (ctypes.c_void_p * n)(*[c._f(x) for c, x in zip(ctxs, xs)])
     sts = (SolveStats * n)()
     hists = []
     for i in range(n):

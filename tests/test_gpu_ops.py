@@ -116,3 +116,27 @@ def test_apply_rejects_aliasing_and_unloaded_gauge():
     with pytest.raises(mspcg.MspcgError) as e:
         ctx.apply(mspcg.OP_D, t, t)
     assert e.value.code == mspcg.EINVAL
+
+
+def test_binding_rejects_fields_of_the_wrong_size():
+    """The C ABI takes bare pointers; the binding checks each field's element
+    count and device against the context before any call, so a field of
+    another lattice never reaches a kernel."""
+    ctx = mspcg.Context((4, 4, 4, 4), 8, 1.8, 0.1)
+    ctx.load_gauge(dev(synth.unit_gauge((4, 4, 4, 4))))
+    t = torch.zeros(ctx.fshape, dtype=torch.complex128, device="cuda")
+    short = torch.zeros(t.numel() - 12, dtype=torch.complex128, device="cuda")
+    with pytest.raises(ValueError):
+        ctx.apply(mspcg.OP_D, t, short)
+    with pytest.raises(ValueError):
+        ctx.solve(short, torch.zeros_like(short), mspcg.make_params())
+    with pytest.raises(ValueError):
+        ctx.load_gauge(torch.zeros(ctx.fshape, dtype=torch.complex128, device="cuda"))
+    with pytest.raises(ValueError):
+        ctx.force(t, t, F=torch.zeros_like(t))
+    with pytest.raises(TypeError):
+        ctx.apply(mspcg.OP_D, t.to(torch.complex64), torch.zeros_like(t))
+    with pytest.raises(ValueError):
+        mspcg.solve_batch([ctx], [t, t], [torch.zeros_like(t)], mspcg.make_params())
+    # a field of the right size still goes through (a flat view included)
+    ctx.apply(mspcg.OP_D, t.reshape(-1), torch.zeros_like(t))

@@ -94,3 +94,11 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stdout
+
+
+def test_field_pointer_checks_need_a_complex128_device_tensor():
+    import torch
+    with pytest.raises(TypeError):
+        mspcg._ptr(torch.zeros(4, dtype=torch.complex128))  # host memory
+    with pytest.raises(TypeError):
+        mspcg._ptr(object())
