@@ -216,8 +216,12 @@ enum {
  * and flagged (mspcg_get_warnings).  *ctx receives the new context, which
  * the caller releases with mspcg_destroy. */
 int mspcg_create(const mspcg_action* action, int device, mspcg_ctx** ctx);
+/* Wait for the context's device, then release every device buffer the
+ * context owns (NULL: no-op). */
 void mspcg_destroy(mspcg_ctx* ctx);
+/* Static text for an MSPCG_* return code. */
 const char* mspcg_strerror(int code);
+/* MSPCG_VERSION of the header the library was built with. */
 int mspcg_version(void);
 /* *warnings = the MSPCG_WARN_* bits of the context's action. */
 int mspcg_get_warnings(mspcg_ctx* ctx, int* warnings);
@@ -304,7 +308,10 @@ int mspcg_solve_batch(mspcg_ctx* const* ctxs, int n, const void* const* b_dev, v
                       const mspcg_solve_params* params, mspcg_solve_stats* stats,
                       hipStream_t stream);
 
-/* Read / replace the context's launch tuning (see mspcg_tuning). */
+/* Read / replace the context's launch tuning (see mspcg_tuning).  Launch
+ * tuning changes no result.  set: every tile extent must be even and >= 0
+ * (MSPCG_EINVAL otherwise); at each launch a preference is clamped to the
+ * largest even extent dividing the box it traverses. */
 int mspcg_get_tuning(mspcg_ctx* ctx, mspcg_tuning* tuning);
 int mspcg_set_tuning(mspcg_ctx* ctx, const mspcg_tuning* tuning);
 
@@ -312,7 +319,8 @@ int mspcg_set_tuning(mspcg_ctx* ctx, const mspcg_tuning* tuning);
  * context's lattice (A in FP64 and FP32; the block operator in FP16 when
  * blocking is not NULL) with HIP events and keeps the fastest.  Results are
  * cached per (dims, Ls, blocking) in the text file cache_path when it is not
- * NULL (read first, appended after tuning).  Needs the gauge field. */
+ * NULL (read first, appended after tuning; a cached line whose tiles
+ * mspcg_set_tuning would reject is skipped).  Needs the gauge field. */
 int mspcg_autotune(mspcg_ctx* ctx, const mspcg_blocking* blocking, const char* cache_path,
                    hipStream_t stream);
 

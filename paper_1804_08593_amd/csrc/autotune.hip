@@ -80,6 +80,12 @@ bool cache_lookup(const char* path, const std::string& key, mspcg_tuning& t) {
                    &r.tile[0][0], &r.tile[0][1], &r.tile[0][2], &r.tile[0][3], &r.tile[1][0],
                    &r.tile[1][1], &r.tile[1][2], &r.tile[1][3], &r.tile[2][0], &r.tile[2][1],
                    &r.tile[2][2], &r.tile[2][3]) == 13) {
+            // the rule of mspcg_set_tuning: a line that breaks it is skipped
+            bool ok = true;
+            for (int p = 0; p < 3; ++p)
+                for (int m = 0; m < 4; ++m) ok = ok && r.tile[p][m] >= 0 && !(r.tile[p][m] & 1);
+            if (!ok) continue;
+            r.xcd_remap = r.xcd_remap ? 1 : 0;
             t = r;
             found = true;
         }

@@ -47,6 +47,16 @@ def test_autotune_and_cache(tmp_path):
     ctx2.load_gauge(dev(U))
     assert ctx2.autotune(blk, 2, cache) == t1
     assert open(cache).read().count("|") == 1
+    # a cached line that mspcg_set_tuning would reject (odd tile) is skipped
+    # and the context tuned afresh
+    bad = str(tmp_path / "bad.txt")
+    with open(bad, "w") as f:
+        f.write("dims=8x8x8x8 Ls=8 block=4x4x4x4 pad=2| remap=1 t64=3,8,8,8 t32=8,8,8,8 "
+                "t16=4,4,4,4\n")
+    t3 = ctx2.autotune(blk, 2, bad)
+    for k in ("fp64", "fp32", "fp16"):
+        assert all(v % 2 == 0 and v >= 0 for v in t3["tile"][k])
+    assert open(bad).read().count("|") == 2
     # the tuned context still solves correctly
     b = synth.fermion_field(dims, Ls, 34)
     x = torch.zeros(ctx.fshape, dtype=torch.complex128, device="cuda")
