@@ -57,13 +57,15 @@ extern "C" {
 enum {
     MSPCG_OK = 0,
     MSPCG_EINVAL = -1,    /* invalid argument (dims, Ls, parameters, null pointer) */
-    MSPCG_ENOMEM = -2,    /* device allocation failed */
+    MSPCG_ENOMEM = -2,    /* device (or host) allocation failed */
     MSPCG_EHIP = -3,      /* a HIP runtime call or kernel launch failed */
     MSPCG_ENOGAUGE = -4,  /* operator used before mspcg_load_gauge */
     MSPCG_ENOCONV = -5,   /* solve stopped at maxiter; x holds the last iterate */
     MSPCG_EBREAKDOWN = -6,/* non-positive curvature or non-finite value in a solve */
     MSPCG_EUNSUPPORTED = -7, /* Ls not compiled in, or an unsupported combination */
-    MSPCG_ESCRATCH = -8   /* lattice too large for the fixed scratch of mspcg_apply_noalloc */
+    MSPCG_ESCRATCH = -8,  /* lattice too large for the fixed scratch of mspcg_apply_noalloc */
+    MSPCG_EINTERNAL = -9  /* unexpected host-side failure inside the library (no C++
+                             exception ever leaves an entry point) */
 };
 
 typedef struct mspcg_ctx mspcg_ctx;

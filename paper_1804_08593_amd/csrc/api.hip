@@ -376,18 +376,19 @@ extern "C" const char* mspcg_strerror(int code) {
     switch (code) {
         case MSPCG_OK: return "ok";
         case MSPCG_EINVAL: return "invalid argument";
-        case MSPCG_ENOMEM: return "device allocation failed";
+        case MSPCG_ENOMEM: return "allocation failed";
         case MSPCG_EHIP: return "HIP runtime error";
         case MSPCG_ENOGAUGE: return "gauge field not loaded";
         case MSPCG_ENOCONV: return "solver did not converge within maxiter";
         case MSPCG_EBREAKDOWN: return "solver breakdown (non-positive curvature or non-finite value)";
         case MSPCG_EUNSUPPORTED: return "unsupported Ls or option";
         case MSPCG_ESCRATCH: return "lattice too large for the fixed scratch of the allocation-free entry point";
+        case MSPCG_EINTERNAL: return "internal host-side failure";
         default: return "unknown error";
     }
 }
 
-extern "C" int mspcg_create(const mspcg_action* a, int device, mspcg_ctx** out) {
+extern "C" int mspcg_create(const mspcg_action* a, int device, mspcg_ctx** out) try {
     if (!a || !out) return MSPCG_EINVAL;
     *out = nullptr;
     for (int m = 0; m < 4; ++m)
@@ -462,8 +463,9 @@ extern "C" int mspcg_create(const mspcg_action* a, int device, mspcg_ctx** out) 
     *out = c;
     return MSPCG_OK;
 }
+MSPCG_ABI_CATCH
 
-extern "C" void mspcg_destroy(mspcg_ctx* c) {
+extern "C" void mspcg_destroy(mspcg_ctx* c) try {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
@@ -481,9 +483,10 @@ extern "C" void mspcg_destroy(mspcg_ctx* c) {
     (void)hipHostFree(c->sc_host);
     for (auto e : c->evpool) (void)hipEventDestroy(e);
     delete c;
+} catch (...) {
 }
 
-extern "C" int mspcg_load_gauge(mspcg_ctx* c, const void* U_dev, hipStream_t st) {
+extern "C" int mspcg_load_gauge(mspcg_ctx* c, const void* U_dev, hipStream_t st) try {
     if (!c || !U_dev) return MSPCG_EINVAL;
     MSPCG_HIP(hipSetDevice(c->device));
     const size_t n = (size_t)4 * c->V4 * 9;
@@ -506,18 +509,21 @@ extern "C" int mspcg_load_gauge(mspcg_ctx* c, const void* U_dev, hipStream_t st)
     c->dom.built = false;  // domain links depend on the gauge field
     return MSPCG_OK;
 }
+MSPCG_ABI_CATCH
 
-extern "C" int mspcg_gauge_generation(mspcg_ctx* c, unsigned long long* gen) {
+extern "C" int mspcg_gauge_generation(mspcg_ctx* c, unsigned long long* gen) try {
     if (!c || !gen) return MSPCG_EINVAL;
     *gen = c->gauge_gen;
     return MSPCG_OK;
 }
+MSPCG_ABI_CATCH
 
-extern "C" int mspcg_get_warnings(mspcg_ctx* c, int* warnings) {
+extern "C" int mspcg_get_warnings(mspcg_ctx* c, int* warnings) try {
     if (!c || !warnings) return MSPCG_EINVAL;
     *warnings = c->warnings;
     return MSPCG_OK;
 }
+MSPCG_ABI_CATCH
 
 template <class S>
 static int apply_prec(mspcg_ctx* c, int op, const double2* in, double2* out, hipStream_t st) {
@@ -598,7 +604,7 @@ static int apply_prec(mspcg_ctx* c, int op, const double2* in, double2* out, hip
 }
 
 extern "C" int mspcg_apply(mspcg_ctx* c, int op, int prec, const void* in_dev, void* out_dev,
-                           hipStream_t st) {
+                           hipStream_t st) try {
     if (!c || !in_dev || !out_dev || in_dev == out_dev) return MSPCG_EINVAL;
     if (!c->gauge) return MSPCG_ENOGAUGE;
     MSPCG_HIP(hipSetDevice(c->device));
@@ -623,6 +629,7 @@ extern "C" int mspcg_apply(mspcg_ctx* c, int op, int prec, const void* in_dev, v
     }
     return apply_op(c, op, prec, (const double2*)in_dev, (double2*)out_dev, st);
 }
+MSPCG_ABI_CATCH
 
 int mspcg::apply_op(mspcg_ctx* c, int op, int prec, const double2* in, double2* out,
                     hipStream_t st) {
@@ -632,13 +639,14 @@ int mspcg::apply_op(mspcg_ctx* c, int op, int prec, const double2* in, double2* 
     return MSPCG_EINVAL;
 }
 
-extern "C" int mspcg_get_tuning(mspcg_ctx* c, mspcg_tuning* t) {
+extern "C" int mspcg_get_tuning(mspcg_ctx* c, mspcg_tuning* t) try {
     if (!c || !t) return MSPCG_EINVAL;
     *t = c->tune;
     return MSPCG_OK;
 }
+MSPCG_ABI_CATCH
 
-extern "C" int mspcg_set_tuning(mspcg_ctx* c, const mspcg_tuning* t) {
+extern "C" int mspcg_set_tuning(mspcg_ctx* c, const mspcg_tuning* t) try {
     if (!c || !t) return MSPCG_EINVAL;
     for (int p = 0; p < 3; ++p)
         for (int m = 0; m < 4; ++m)
@@ -647,8 +655,9 @@ extern "C" int mspcg_set_tuning(mspcg_ctx* c, const mspcg_tuning* t) {
     c->tune.xcd_remap = t->xcd_remap ? 1 : 0;
     return MSPCG_OK;
 }
+MSPCG_ABI_CATCH
 
-extern "C" int mspcg_set_blocking(mspcg_ctx* c, const mspcg_blocking* b) {
+extern "C" int mspcg_set_blocking(mspcg_ctx* c, const mspcg_blocking* b) try {
     if (!c || !b) return MSPCG_EINVAL;
     for (int m = 0; m < 4; ++m) {
         if (b->block[m] < 2 || (b->block[m] & 1) || c->L[m] % b->block[m]) return MSPCG_EINVAL;
@@ -660,9 +669,10 @@ extern "C" int mspcg_set_blocking(mspcg_ctx* c, const mspcg_blocking* b) {
     c->has_blocking = true;
     return MSPCG_OK;
 }
+MSPCG_ABI_CATCH
 
 extern "C" int mspcg_precond(mspcg_ctx* c, int inner_iters, int prec, const void* r_dev,
-                             void* z_dev, hipStream_t st) {
+                             void* z_dev, hipStream_t st) try {
     if (!c || !r_dev || !z_dev || r_dev == z_dev || inner_iters < 0) return MSPCG_EINVAL;
     if (!c->gauge) return MSPCG_ENOGAUGE;
     if (!c->has_blocking) return MSPCG_EINVAL;
@@ -684,19 +694,21 @@ extern "C" int mspcg_precond(mspcg_ctx* c, int inner_iters, int prec, const void
         return MSPCG_EHIP;
     return MSPCG_OK;
 }
+MSPCG_ABI_CATCH
 
 extern "C" int mspcg_solve(mspcg_ctx* c, const void* b_dev, void* x_dev,
                            const mspcg_solve_params* p, mspcg_solve_stats* stats,
-                           hipStream_t st) {
+                           hipStream_t st) try {
     if (!c || !b_dev || !x_dev || !p || b_dev == x_dev) return MSPCG_EINVAL;
     if (!c->gauge) return MSPCG_ENOGAUGE;
     MSPCG_HIP(hipSetDevice(c->device));
     return solve_one(c, b_dev, x_dev, p, stats, st);
 }
+MSPCG_ABI_CATCH
 
 extern "C" int mspcg_pseudofermion_action(mspcg_ctx* c, const void* phi_dev, void* X_dev,
                                           void* dphi_dev, const mspcg_solve_params* p,
-                                          double* S, mspcg_solve_stats* stats, hipStream_t st) {
+                                          double* S, mspcg_solve_stats* stats, hipStream_t st) try {
     if (!c || !phi_dev || !X_dev || !p || !S || phi_dev == X_dev || dphi_dev == phi_dev ||
         dphi_dev == X_dev)
         return MSPCG_EINVAL;
@@ -725,10 +737,12 @@ extern "C" int mspcg_pseudofermion_action(mspcg_ctx* c, const void* phi_dev, voi
     *S = v;
     return rc;
 }
+MSPCG_ABI_CATCH
 
 extern "C" int mspcg_solve_batch(mspcg_ctx* const* ctxs, int n, const void* const* b_dev,
                                  void* const* x_dev, const mspcg_solve_params* p,
-                                 mspcg_solve_stats* stats, hipStream_t st) {
+                                 mspcg_solve_stats* stats, hipStream_t st) try {
     if (!ctxs || n < 0 || !b_dev || !x_dev || !p) return MSPCG_EINVAL;
     return solve_batch(ctxs, n, b_dev, x_dev, p, stats, st);
 }
+MSPCG_ABI_CATCH

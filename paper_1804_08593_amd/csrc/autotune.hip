@@ -111,7 +111,7 @@ void cache_store(const char* path, const std::string& key, const mspcg_tuning& t
 using namespace mspcg;
 
 extern "C" int mspcg_autotune(mspcg_ctx* c, const mspcg_blocking* bk, const char* cache_path,
-                              hipStream_t st) {
+                              hipStream_t st) try {
     if (!c) return MSPCG_EINVAL;
     if (!c->gauge) return MSPCG_ENOGAUGE;
     MSPCG_HIP(hipSetDevice(c->device));
@@ -188,6 +188,7 @@ extern "C" int mspcg_autotune(mspcg_ctx* c, const mspcg_blocking* bk, const char
     if (cache_path) cache_store(cache_path, key, t);
     return MSPCG_OK;
 }
+MSPCG_ABI_CATCH
 
 // ---------------------------------------------------------------------------
 // Block-shape selection for MSPCG
@@ -236,7 +237,7 @@ std::vector<mspcg_blocking> block_candidates(const mspcg_ctx* c, int pad, int fo
 }  // namespace
 
 extern "C" int mspcg_tune_blocking(mspcg_ctx* c, const mspcg_solve_params* base, int probe_iters,
-                                   mspcg_blocking* chosen, hipStream_t st) {
+                                   mspcg_blocking* chosen, hipStream_t st) try {
     if (!c || !base || probe_iters < 1) return MSPCG_EINVAL;
     if (!c->gauge) return MSPCG_ENOGAUGE;
     MSPCG_HIP(hipSetDevice(c->device));
@@ -285,3 +286,4 @@ extern "C" int mspcg_tune_blocking(mspcg_ctx* c, const mspcg_solve_params* base,
     if (chosen) *chosen = bestb;
     return MSPCG_OK;
 }
+MSPCG_ABI_CATCH

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <new>
 #include <memory>
 #include <string>
 #include <vector>
@@ -11,6 +12,13 @@
 #include "../../include/mspcg.h"
 #include "common.h"
 #include "kernels.h"
+
+// Closes an entry point written as a function-try-block, so that no C++
+// exception leaves the C ABI: host allocation failures report MSPCG_ENOMEM,
+// anything else MSPCG_EINTERNAL.
+#define MSPCG_ABI_CATCH                                  \
+    catch (const std::bad_alloc&) { return MSPCG_ENOMEM; } \
+    catch (...) { return MSPCG_EINTERNAL; }
 
 namespace mspcg {
 

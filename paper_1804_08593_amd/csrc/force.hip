@@ -261,7 +261,7 @@ __global__ __launch_bounds__(FORCE_THREADS, 3) void force_kernel(ForceArgs a) {
 using namespace mspcg;
 
 extern "C" int mspcg_force(mspcg_ctx* c, const void* X_dev, const void* Y_dev, void* F_dev,
-                           void* G_dev, hipStream_t st) {
+                           void* G_dev, hipStream_t st) try {
     if (!c || !X_dev || !Y_dev || (!F_dev && !G_dev)) return MSPCG_EINVAL;
     if (!c->gauge) return MSPCG_ENOGAUGE;
     MSPCG_HIP(hipSetDevice(c->device));
@@ -312,3 +312,4 @@ extern "C" int mspcg_force(mspcg_ctx* c, const void* X_dev, const void* Y_dev, v
     MSPCG_HIP(hipStreamSynchronize(st));
     return MSPCG_OK;
 }
+MSPCG_ABI_CATCH

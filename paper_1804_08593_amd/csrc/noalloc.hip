@@ -61,7 +61,7 @@ int mspcg::noalloc_init(int device) {
 }
 
 extern "C" int mspcg_apply_noalloc(mspcg_ctx* c, int op, int prec, const void* in_dev,
-                                   void* out_dev, hipStream_t st) {
+                                   void* out_dev, hipStream_t st) try {
     if (!c || !in_dev || !out_dev || in_dev == out_dev) return MSPCG_EINVAL;
     if (op == MSPCG_OP_KBLOCK) return MSPCG_EUNSUPPORTED;
     if (op < 0 || op > MSPCG_OP_PREPARE) return MSPCG_EINVAL;
@@ -83,3 +83,4 @@ extern "C" int mspcg_apply_noalloc(mspcg_ctx* c, int op, int prec, const void* i
     c->timing = timing;
     return e == MSPCG_ENOMEM ? MSPCG_ESCRATCH : e;
 }
+MSPCG_ABI_CATCH

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_PKG, "libmspcg.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOGAUGE, ENOCONV, EBREAKDOWN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 ESCRATCH = -8
+EINTERNAL = -9
 NOALLOC_SCRATCH_BYTES = 128 << 20
 OP_D, OP_DDAG, OP_HOP, OP_HOPDAG, OP_MHAT, OP_MHATDAG, OP_A, OP_M5INV, OP_PREPARE, OP_KBLOCK = range(10)
 FP64, FP32, FP16 = 0, 1, 2

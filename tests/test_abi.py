@@ -27,9 +27,41 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_strerror_texts():
-    for code in (0, -1, -2, -3, -4, -5, -6, -7):
-        assert mspcg.strerror(code)
+    codes = (mspcg.OK, mspcg.EINVAL, mspcg.ENOMEM, mspcg.EHIP, mspcg.ENOGAUGE, mspcg.ENOCONV,
+             mspcg.EBREAKDOWN, mspcg.EUNSUPPORTED, mspcg.ESCRATCH, mspcg.EINTERNAL)
+    for code in codes:
+        assert mspcg.strerror(code) != "unknown error"
+    assert len(set(codes)) == len(codes)
     assert mspcg.strerror(-99) == "unknown error"
+
+
+def test_no_exception_leaves_an_entry_point():
+    """Every entry point that does more than return a constant is a
+    function-try-block closed by the catch clauses that map C++ exceptions to
+    error codes."""
+    csrc = os.path.join(ROOT, "paper_1804_08593_amd", "csrc")
+    seen = set()
+    for fn in sorted(os.listdir(csrc)):
+        if not fn.endswith(".hip"):
+            continue
+        lines = open(os.path.join(csrc, fn)).read().split("\n")
+        for i, ln in enumerate(lines):
+            if not ln.startswith('extern "C"'):
+                continue
+            name = re.search(r"(mspcg_\w+)\(", ln).group(1)
+            seen.add(name)
+            if name in ("mspcg_version", "mspcg_strerror"):
+                continue
+            j = i
+            while not lines[j].rstrip().endswith("{"):
+                j += 1
+            assert lines[j].rstrip().endswith(") try {"), name
+            k = j + 1
+            while lines[k] != "}" and not lines[k].startswith("} catch"):
+                k += 1
+            closing = lines[k] + lines[k + 1]
+            assert "MSPCG_ABI_CATCH" in closing or lines[k].startswith("} catch (...)"), name
+    assert seen == set(_declared())
 
 
 @pytest.mark.parametrize("dims,Ls,err", [
