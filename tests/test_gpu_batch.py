@@ -104,6 +104,35 @@ def test_persistent_multi_lattice_launch_matches_per_lattice_launches(prec):
     say(f"persistent vs per-lattice launches bitwise identical: {bitwise}")
 
 
+def test_persistent_batch_mixed_readings():
+    """One persistent batch whose lattices use different readings of A_s
+    (Dirichlet pad 0, the split form, pad 1): the same iterations and x as
+    per-lattice launches, and oracle-checked residuals."""
+    readings = [(0, mspcg.FORM_DOMAIN), (2, mspcg.FORM_SPLIT), (1, mspcg.FORM_DOMAIN)]
+    sys = [_make(d, Ls, mf, 0.25, 80 + i, 90 + i) for i, (d, Ls, mf, _) in enumerate(MULTI)]
+    for (ctx, _, _), (d, Ls, mf, blk), (pad, form) in zip(sys, MULTI, readings):
+        ctx.set_blocking(blk, pad, form)
+    out = {}
+    for kern in (0, 1):
+        prm = mspcg.make_params(tol=1e-10, maxiter=3000, solver=mspcg.SOLVER_MSPCG,
+                                inner_iters=4, inner_prec=mspcg.FP16, batch_kernels=kern)
+        xs = [torch.zeros_like(b) for _, _, b in sys]
+        sts = mspcg.solve_batch([c for c, _, _ in sys], [b for _, _, b in sys], xs, prm)
+        out[kern] = (xs, sts)
+        for st in sts:
+            assert st["converged"] and st["batch_persistent"] == (kern == 0)
+    for i, (d, Ls, mf, blk) in enumerate(MULTI):
+        (xa, sa), (xb, sb) = (out[0][0][i], out[0][1][i]), (out[1][0][i], out[1][1][i])
+        say(f"lattice {d} Ls={Ls} pad/form {readings[i]}: persistent {sa['outer_iters']} it, "
+            f"per-lattice {sb['outer_iters']} it")
+        assert sa["outer_iters"] == sb["outer_iters"]
+        assert relerr(host(xa), host(xb)) <= 1e-12
+        act = O.Action(d, Ls, 1.8, mf, 1.5, 0.5)
+        _, bhat = O.prepare(act, sys[i][1], host(sys[i][2]))
+        r = bhat - O.normal(act, sys[i][1], O.parity_mask(act, host(xa), 0))
+        assert np.sqrt(O.norm2(r) / O.norm2(bhat)) <= 1e-10 * 1.01
+
+
 def test_persistent_batch_degenerate_members():
     """Degenerate batches on the persistent path: a member with a zero
     right-hand side (x = 0, no iterations, left out of the others' launches),
