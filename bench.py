@@ -21,6 +21,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -417,6 +418,51 @@ def sweep_blocks(ctx, w, bd, x, args, log):
             log(f"[blocks] {blk} l={l}: {st['outer_iters']} it {st['seconds']:.3f} s")
 
 
+def tuner_check(ctx, w, bd, x, args, log):
+    """The block-shape tuner's candidates (every set of halved directions and
+    one quartering) on the workload: the tuner's score (-log of the relative
+    residual after 8 outer iterations per second), the slope over iterations
+    8..24, and the true time to the tolerance; then the tuner's own pick."""
+    from paper_1804_08593_amd import mspcg
+
+    L = w["dims"]
+    cands = [tuple(L[m] // 2 if (mask >> m) & 1 else L[m] for m in range(4)) for mask in range(1, 16)]
+    cands.append(tuple(L[m] // 4 if L[m] >= 16 else L[m] // 2 for m in range(4)))
+    rows = []
+    for blk in cands:
+        if any(L[m] % blk[m] or blk[m] % 2 or (L[m] != blk[m] and L[m] - blk[m] < 4)
+               for m in range(4)):
+            continue
+        t, hist = {}, None
+        for k in (8, 24):
+            p = mspcg.make_params(tol=1e-300, maxiter=k, solver=mspcg.SOLVER_MSPCG, block=blk,
+                                  pad=2, inner_iters=args.inner_iters, inner_prec=mspcg.FP16)
+            if k == 8:
+                ctx.solve(bd, x, p, allow_noconv=True)  # domain set-up
+            st = ctx.solve(bd, x, p, allow_noconv=True, history=k)
+            t[k] = st["seconds"]
+            hist = st["history"]
+        p = mspcg.make_params(tol=args.tol, maxiter=20000, solver=mspcg.SOLVER_MSPCG, block=blk,
+                              pad=2, inner_iters=args.inner_iters, inner_prec=mspcg.FP16)
+        st = min((ctx.solve(bd, x, p) for _ in range(2)), key=lambda r: r["seconds"])
+        row = {"workload": args.workload, "block": list(blk),
+               "score_8": round(-math.log(hist[7]) / t[8], 3),
+               "slope_8_24": round((math.log(hist[7]) - math.log(hist[23])) / (t[24] - t[8]), 3),
+               "outer_iters": st["outer_iters"], "seconds": round(st["seconds"], 4)}
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+        log(f"[tuner] {blk}: {st['outer_iters']} it {st['seconds']:.3f} s")
+    blk, pad = ctx.tune_blocking(mspcg.make_params(tol=args.tol, solver=mspcg.SOLVER_MSPCG, pad=2,
+                                                   inner_iters=args.inner_iters,
+                                                   inner_prec=mspcg.FP16))
+    ts = np.argsort(np.argsort([r["seconds"] for r in rows]))
+    sc = np.argsort(np.argsort([-r["score_8"] for r in rows]))
+    print(json.dumps({"workload": args.workload, "tuner_pick": list(blk),
+                      "fastest": min(rows, key=lambda r: r["seconds"])["block"],
+                      "rank_correlation_score_8": round(float(np.corrcoef(ts, sc)[0, 1]), 3)}),
+          flush=True)
+
+
 def tile_sweep(ctx, w, bd, x, args, log):
     """FP64 dslash time for each traversal tile in --tiles (AxBxCxD,...):
     60 plain CG iterations with per-class HIP-event timing per tile."""
@@ -486,6 +532,8 @@ def main():
                     help="instead of the bench line: MSPCG with the workload's blocks for "
                          "every block reading (Dirichlet, pad 1, split Schur, literal) and "
                          "l = 2..8, one JSON line per solve")
+    ap.add_argument("--tuner-check", action="store_true",
+                    help="block-shape tuner's candidates: its score vs the true time to solve")
     ap.add_argument("--sweep-blocks", action="store_true",
                     help="MSPCG time per block shape and l on the workload, then exit")
     ap.add_argument("--tiles", default=None,
@@ -555,6 +603,9 @@ def main():
         return
     if args.sweep_blocks:
         sweep_blocks(ctx, w, bd, x, args, log)
+        return
+    if args.tuner_check:
+        tuner_check(ctx, w, bd, x, args, log)
         return
 
     p_cg = mspcg.make_params(tol=args.tol, maxiter=20000, solver=mspcg.SOLVER_CG, timing=True)
