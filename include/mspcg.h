@@ -331,8 +331,12 @@ int mspcg_autotune(mspcg_ctx* ctx, const mspcg_blocking* blocking, const char* c
  * directions, or quartering long ones, where the padded domain still fits),
  * runs probe_iters outer iterations of MSPCG with
  * base's local-solve settings on a fixed synthetic right-hand side and keeps
- * the blocking with the fastest residual reduction per second.  The choice
- * becomes the context's blocking and is returned in chosen (may be NULL). */
+ * the blocking with the fastest residual reduction per second; probe_iters = 0
+ * instead solves every candidate to base's tolerance and keeps the shortest
+ * time to solution (slower to tune, and the only reliable choice when a
+ * blocking's advantage shows only late in the solve).  The choice becomes the
+ * context's blocking and is returned in chosen (may be NULL).  probe_iters < 0:
+ * MSPCG_EINVAL. */
 int mspcg_tune_blocking(mspcg_ctx* ctx, const mspcg_solve_params* base, int probe_iters,
                         mspcg_blocking* chosen, hipStream_t stream);
 

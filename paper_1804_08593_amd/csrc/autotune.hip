@@ -238,7 +238,11 @@ std::vector<mspcg_blocking> block_candidates(const mspcg_ctx* c, int pad, int fo
 
 extern "C" int mspcg_tune_blocking(mspcg_ctx* c, const mspcg_solve_params* base, int probe_iters,
                                    mspcg_blocking* chosen, hipStream_t st) try {
-    if (!c || !base || probe_iters < 1) return MSPCG_EINVAL;
+    if (!c || !base || probe_iters < 0) return MSPCG_EINVAL;
+    if (probe_iters == 0 && !(base->tol > 0)) return MSPCG_EINVAL;
+    // probe_iters == 0: every candidate is solved to base's tolerance and the
+    // shortest time to solution decides
+    const bool full = probe_iters == 0;
     if (!c->gauge) return MSPCG_ENOGAUGE;
     MSPCG_HIP(hipSetDevice(c->device));
     const int pad = base->blocking.pad > 0 || base->blocking.block[0] ? base->blocking.pad : 2;
@@ -254,28 +258,39 @@ extern "C" int mspcg_tune_blocking(mspcg_ctx* c, const mspcg_solve_params* base,
     if (hipGetLastError() != hipSuccess) return MSPCG_EHIP;
     mspcg_solve_params p = *base;
     p.solver = MSPCG_SOLVER_MSPCG;
-    p.maxiter = probe_iters;
-    p.tol = 1e-300;
+    p.maxiter = full ? (base->maxiter > 0 ? base->maxiter : 20000) : probe_iters;
+    p.tol = full ? base->tol : 1e-300;
     p.use_x0 = 0;
     p.timing = 0;
     p.rhs_normal = 0;
     double best = -1;
     mspcg_blocking bestb = cands[0];
-    std::vector<double> hist(probe_iters + 1);
+    std::vector<double> hist(full ? 1 : probe_iters + 1);
     for (const mspcg_blocking& cb : cands) {
         p.blocking = cb;
         mspcg_solve_stats s;
         memset(&s, 0, sizeof(s));
         s.resid_history = hist.data();
-        s.resid_history_cap = probe_iters;
-        int e = solve_one(c, b, x, &p, &s, st);  // first run also builds the domain links
+        s.resid_history_cap = full ? 0 : probe_iters;
+        // a first, short run builds the domain links outside the timed one
+        mspcg_solve_params p1 = p;
+        p1.maxiter = full ? 1 : p.maxiter;
+        p1.tol = 1e-300;
+        int e = solve_one(c, b, x, &p1, &s, st);
         if (e != MSPCG_OK && e != MSPCG_ENOCONV) return e;
         e = solve_one(c, b, x, &p, &s, st);
         if (e != MSPCG_OK && e != MSPCG_ENOCONV) return e;
-        if (s.resid_history_len < 1 || !(s.seconds > 0)) continue;
-        const double r = hist[s.resid_history_len - 1];
-        if (!(r > 0)) continue;
-        const double rate = -log(r) / s.seconds;  // e-folds of residual per second
+        if (!(s.seconds > 0)) continue;
+        double rate;
+        if (full) {
+            if (e != MSPCG_OK) continue;  // did not reach the tolerance
+            rate = 1.0 / s.seconds;
+        } else {
+            if (s.resid_history_len < 1) continue;
+            const double r = hist[s.resid_history_len - 1];
+            if (!(r > 0)) continue;
+            rate = -log(r) / s.seconds;  // e-folds of residual per second
+        }
         if (rate > best) {
             best = rate;
             bestb = cb;

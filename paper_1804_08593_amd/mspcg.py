@@ -323,7 +323,9 @@ class Context:
         return self.get_tuning().as_dict()
 
     def tune_blocking(self, params: "SolveParams" = None, probe_iters=8, stream=None):
-        """Pick the MSPCG block shape with the fastest residual reduction per second."""
+        """Pick the MSPCG block shape: fastest residual reduction per second over
+        probe_iters outer iterations, or (probe_iters = 0) shortest time to
+        solve each candidate to params' tolerance."""
         p = params if params is not None else make_params(solver=SOLVER_MSPCG)
         b = Blocking()
         _check(load().mspcg_tune_blocking(self._h, ctypes.byref(p), int(probe_iters),

@@ -71,3 +71,29 @@ def test_set_tuning_rejects_odd_tiles():
     ctx = mspcg.Context((4, 4, 4, 4), 8, 1.8, 0.1)
     with pytest.raises(mspcg.MspcgError):
         ctx.set_tuning(1, (3, 4, 4, 4))
+
+
+def test_tune_blocking_short_probe_and_full_solves():
+    """Both block-shape tuner modes return one of its candidates (every set of
+    halved directions) as the context's blocking, and MSPCG with that
+    blocking (params' block left at zero) reaches the oracle-checked
+    residual; a negative probe length is rejected."""
+    dims, Ls = (8, 8, 8, 8), 8
+    act, U, ctx = setup(dims, Ls, 1.8, 0.05, 1.5, 0.5, gseed=35)
+    base = mspcg.make_params(tol=1e-10, maxiter=3000, solver=mspcg.SOLVER_MSPCG, inner_iters=4,
+                             inner_prec=mspcg.FP16)
+    b = synth.fermion_field(dims, Ls, 36)
+    _, bhat = O.prepare(act, U, b)
+    for k in (6, 0):
+        blk, pad = ctx.tune_blocking(base, probe_iters=k)
+        say(f"probe_iters={k}: blocking {blk} pad {pad}")
+        assert pad == 2 and blk != tuple(dims)
+        assert all(v in (L, L // 2) for v, L in zip(blk, dims))
+        x = torch.zeros(ctx.fshape, dtype=torch.complex128, device="cuda")
+        st = ctx.solve(dev(b), x, base)
+        assert st["converged"]
+        r = bhat - O.normal(act, U, O.parity_mask(act, host(x), 0))
+        assert (O.norm2(r) / O.norm2(bhat)) ** 0.5 <= 1e-10 * 1.01
+    with pytest.raises(mspcg.MspcgError) as e:
+        ctx.tune_blocking(base, probe_iters=-1)
+    assert e.value.code == mspcg.EINVAL
